@@ -1,0 +1,183 @@
+#!/usr/bin/env python3
+"""Throughput of the multiple-double series Newton path on one MI355X.
+
+Workload (quad double, complex; the 32-unknown, degree-16 configuration):
+one step is
+  * md_poly_eval_diff: a 32 x 32 polynomial system, 16 monomials of degree
+    <= 4 per equation, unit complex coefficients, at a series point with
+    unit complex coefficients, truncation degree d = 16;
+  * md_qr: Householder QR of A_0 (32 x 32, A_0 = U diag(s) U^H with
+    condition number 1e3);
+  * md_series_solve: the staggered solve of A(t) dx(t) = b(t), d = 16, with
+    A_1..A_16 and b unit complex,
+i.e. the kernels of one Newton step at this size.  Inputs are seeded,
+synthetic and resident in HBM before timing.
+
+Prints one JSON line: steps/s, the fraction of the FP64 vector peak reached
+by the step's algorithmic work (Table 1 operation counts), the roofline of
+the dominant kernel, and the CPU oracle timed on the host on the same
+inputs.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "multiple-double series Newton steps/s and % of FP64 vector peak"
+M, N, D = 4, 32, 16
+WORKLOAD = ("qd complex, n=N=32, d=16: eval/diff of a 32x32 system (16 monomials of degree<=4 "
+            "per equation) + Householder QR of A0 (cond 1e3) + staggered block Toeplitz solve")
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="wall time budget of the CPU oracle baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def make_inputs():
+    from paper_2012_06607_amd import inputs as I
+    sysm = I.eval_system((2, 0), N, N, M, 16, 4)
+    x = I.unit_series((2, 1), M, D, N)
+    A, b = I.toeplitz_system((2, N), N, D, M)
+    return sysm, x, A, b
+
+
+def cpu_baseline(sysm, x, A, b, budget_s: float) -> dict:
+    """The oracle, single threaded, on the same inputs: full steps until the
+    time budget is spent."""
+    import oracle
+    oracle.build()
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        oracle.eval_diff(sysm, x)
+        QR, vd, beta, _ = oracle.qr(A[:, :, 0])
+        oracle.series_solve(QR, vd, beta, A, b)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return {"value": steps / el, "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} full steps of the same workload on one host thread "
+                      f"({el:.1f} s, gcc -O2 C oracle)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
+              f"multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2012_06607_amd import binding as B
+    from paper_2012_06607_amd import opcount as OC
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    B.lib()
+    sysm, x_h, A_h, b_h = make_inputs()
+    dev = torch.device("cuda")
+    sd = B.DeviceSystem(sysm)
+    x = torch.as_tensor(x_h, device=dev)
+    A = torch.as_tensor(A_h, device=dev)
+    b = torch.as_tensor(b_h, device=dev)
+    A0 = A[:, :, 0].contiguous()
+    f = torch.empty((2, M, D + 1, N), dtype=torch.float64, device=dev)
+    Aev = torch.empty((2, M, D + 1, N, N), dtype=torch.float64, device=dev)
+    dx = torch.empty((2, M, D + 1, N), dtype=torch.float64, device=dev)
+    ws_eval = B.workspace(B.MD_FN_EVAL, M, N, N, D, sysm.M, sysm.max_deg, dev)
+    ws_solve = B.workspace(B.MD_FN_SOLVE, M, N, N, D, 0, 0, dev)
+    QRb = torch.empty_like(A0)
+    vdb = torch.empty((2, M, N), dtype=torch.float64, device=dev)
+    betab = torch.empty((M, N), dtype=torch.float64, device=dev)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        B.md_poly_eval_diff(sd, x, f, Aev, ws_eval, stream)
+        if ev is not None:
+            ev[1].record(stream)
+        QR, vd, beta, _ = B.md_qr(A0, status, stream, QRb, vdb, betab)
+        if ev is not None:
+            ev[2].record(stream)
+        B.md_series_solve(QR, vd, beta, A, b, dx, ws_solve, status, stream)
+        if ev is not None:
+            ev[3].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    K = args.steps
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for s in range(K):
+        step(evs[s])
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    total_ms = t_start.elapsed_time(t_end)
+    ms_per_step = total_ms / K
+    st = int(status.item())
+
+    names = ("md_poly_eval_diff", "md_qr", "md_series_solve")
+    dur = {nm: float(np.mean([evs[s][i].elapsed_time(evs[s][i + 1]) for s in range(K)]))
+           for i, nm in enumerate(names)}
+    ops = {"md_poly_eval_diff": OC.eval_diff(sysm, D).table_ops(M),
+           "md_qr": OC.qr(N, N, M).table_ops(M),
+           "md_series_solve": OC.series_solve(N, N, D).table_ops(M)}
+    step_ops = sum(ops.values())
+    dom = max(dur, key=dur.get)
+    achieved = ops[dom] / (dur[dom] * 1e-3) / 1e12
+    peak = OC.FP64_VECTOR_PEAK / 1e12
+    value = 1000.0 / ms_per_step
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "precision": "quad double (m=4)", "n": N, "N": N, "d": D,
+                   "monomials_per_equation": 16, "max_degree": 4, "cond_A0": 1e3},
+        "pct_fp64_vector_peak": round(100.0 * step_ops * value / OC.FP64_VECTOR_PEAK, 3),
+        "table_ops_per_step": step_ops,
+        "kernels_ms": {k: round(v, 4) for k, v in dur.items()},
+        "roofline": {"kernel": dom, "bound": "alu", "achieved": round(achieved, 4),
+                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 5),
+                     "traffic": None,
+                     "basis": "Table 1 hardware-double operations of the entry point's "
+                              "multiple-double operations per launch / mean launch time"},
+        "status": st,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(sysm, x_h, A_h, b_h, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,178 @@
+/*
+ * mdseries: one Newton step on truncated power series in complex
+ * multiple-double precision, on AMD Instinct MI355X (gfx950).
+ *
+ * Method: J. Verschelde, "Parallel Software to Offset the Cost of Higher
+ * Precision", arXiv:2012.06607.  Section 2 defines multiple doubles,
+ * Section 3 truncated power series and their product, Section 4 Newton's
+ * method on series: evaluation and reverse-mode differentiation of the
+ * system, then the block lower triangular Toeplitz solve with one QR of A_0.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Numbers.  A multiple double with m limbs (m in {1,2,3,4,5,8,10}: double,
+ *   double double, triple, quad, penta, octo, deca double) is an unevaluated
+ *   sum of m doubles, limb 0 the most significant (Section 2).
+ * Layout.  A complex multiple-double tensor of logical shape S is a
+ *   contiguous float64 array of 2*m*|S| doubles: planes (2, m, S...), the
+ *   real part first; element e (row-major index into S) has real limb l at
+ *   p[l*|S| + e] and imaginary limb l at p[(m+l)*|S| + e].  Real tensors are
+ *   planes (m, S...).  Series vectors are coefficient-major: a series
+ *   x(t) = x_0 + x_1 t + ... + x_d t^d of n-vectors has shape (d+1, n); a
+ *   matrix series has shape (d+1, N, n) (Section 4: power series with vector
+ *   and matrix coefficients).  Inputs must be normalised expansions.
+ * Memory.  Every double* / int32_t* argument is a DEVICE pointer (HIP device
+ *   memory) owned by the caller; the library never allocates or frees device
+ *   memory.  Scratch space is a caller-provided device workspace of at least
+ *   md_workspace_bytes(...) bytes, 256-byte aligned.
+ * Streams.  `stream` is a hipStream_t (0 = null stream).  Calls only enqueue
+ *   work on it: they are asynchronous and never synchronise.
+ * Errors.  Argument errors are returned at once as an MD_E* code with a
+ *   message in md_last_error() (thread local); nothing is enqueued then.
+ *   Numerical conditions found on the device are OR-ed into the caller's
+ *   device word *status (when status is not NULL) as MD_ST_* bits; read it
+ *   after synchronising the stream.  Callers clear *status before a call.
+ * Aliasing.  Outputs must not overlap inputs, except the in/out x of
+ *   md_newton_step.
+ * Determinism.  Every reduction has a fixed order: the same call on the
+ *   same inputs gives the same bits.
+ */
+#ifndef MDSERIES_H
+#define MDSERIES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MD_OK = 0,
+  MD_EINVAL = 1,     /* bad m, negative degree or count, unknown op */
+  MD_ESHAPE = 2,     /* n < 1, N < n, or sizes out of the supported range */
+  MD_ENULL = 3,      /* a required pointer is NULL */
+  MD_EWORKSPACE = 4, /* workspace missing, too small or misaligned */
+  MD_EHIP = 5        /* a kernel launch failed */
+};
+
+enum {
+  MD_ST_SINGULAR = 1, /* a Householder column or a diagonal of R is zero */
+  MD_ST_NONFINITE = 2 /* an infinity or NaN reached a result */
+};
+
+/* Polynomial system f = (f_1..f_N) in x = (x_1..x_n), N >= n, whose terms
+ * are c(t) x^a with truncated power series coefficients c(t) (Section 4).
+ * All pointers are device pointers.
+ *   eq_ptr   int32 [N+1]: the terms of equation i are eq_ptr[i]..eq_ptr[i+1]-1
+ *   term_ptr int32 [M+1]: the factors of term j are
+ *            factors[term_ptr[j]..term_ptr[j+1]-1]
+ *   factors  int32 [F]: variable indices in [0, n), with repetition for
+ *            powers, non-decreasing within a term; a term without factors is
+ *            a constant (a coefficient c(t) alone)
+ *   coef     planes (2, m, M, dc+1): coefficient series, degree dc
+ * max_deg must be the largest number of factors of a term (host value). */
+typedef struct md_system {
+  int32_t N, n, M, dc, max_deg;
+  const int32_t *eq_ptr;
+  const int32_t *term_ptr;
+  const int32_t *factors;
+  const double *coef;
+} md_system;
+
+/* Truncated series product (Section 3): z_k = sum_{i=0}^{k} x_i y_{k-i},
+ * k = 0..d, for `count` independent pairs of series; each z_k starts from
+ * its first product x_0 y_k and adds the others in increasing i, i.e.
+ * (d+2)(d+1)/2 multiplications and (d+1)d/2 additions per pair.
+ * x, y, z: planes (2, m, count, d+1).  Errors: MD_EINVAL (m, d < 0,
+ * count < 0), MD_ENULL. */
+int md_series_convolve(int m, int d, int64_t count, const double *x, const double *y, double *z,
+                       void *stream);
+
+/* Evaluation and reverse-mode differentiation of a system at a series point
+ * (Section 4, algorithmic differentiation: all n partial derivatives for a
+ * small multiple of the cost of the value).  For each term with factor list
+ * v_1..v_D the forward products P_j = v_1 ... v_j, backward products
+ * Q_j = v_j ... v_D and cross products C_j = P_{j-1} Q_{j+1} give the value
+ * P_D and each partial derivative a_l C_{j*} (j* the first position of x_l,
+ * a_l its multiplicity); both are multiplied by c(t) and added into f_i and
+ * A_{i,l} in term order.
+ * x: planes (2, m, d+1, n) -> f: (2, m, d+1, N), A: (2, m, d+1, N, n)
+ * (A_k = coefficient k of the Jacobian series).  Workspace:
+ * md_workspace_bytes(MD_FN_EVAL, m, N, n, d, M, max_deg).
+ * Errors: MD_EINVAL, MD_ESHAPE, MD_ENULL, MD_EWORKSPACE. */
+int md_poly_eval_diff(int m, int d, const md_system *sys, const double *x, double *f, double *A,
+                      void *ws, size_t ws_bytes, void *stream);
+
+/* Householder QR of A0 (N x n, N >= n), the one factorisation the block
+ * Toeplitz solve needs (Section 4).  A0 = Q R with Q = H_0 ... H_{n-1},
+ * H_j = I - beta_j v_j v_j^H on rows j..N-1; for column j with alpha its
+ * diagonal entry and sigma its 2-norm from the diagonal down:
+ * phi = alpha/|alpha| (1 if alpha = 0), v_j = (phi (|alpha| + sigma), the
+ * entries below the diagonal), beta_j = 1/(sigma (sigma + |alpha|)),
+ * R_jj = -phi sigma.  Q is never formed.
+ * A0: planes (2, m, N, n) row-major; QR: (2, m, N, n) holds R on and above
+ * the diagonal and the reflector tails below it; vdiag: (2, m, n) reflector
+ * heads; beta: real planes (m, n).  A zero column sets MD_ST_SINGULAR
+ * (beta_j = 0, R_jj = 0).  Errors: MD_EINVAL, MD_ESHAPE, MD_ENULL. */
+int md_qr(int m, int N, int n, const double *A0, double *QR, double *vdiag, double *beta,
+          int32_t *status, void *stream);
+
+/* Solution of the linearised system A(t) dx(t) = b(t), the block lower
+ * triangular Toeplitz system of Section 4, by forward substitution over the
+ * degrees: A_0 dx_k = b_k - A_1 dx_{k-1} - ... - A_k dx_0, k = 0..d, each
+ * stage solved with the QR factors of A_0 (Q^H, then back substitution with
+ * R; least squares in the first n rows when N > n).  The stages run in
+ * order; within a stage all right hand side updates r_{k+j} -= A_j dx_k run
+ * in parallel.
+ * QR, vdiag, beta: outputs of md_qr; A: planes (2, m, d+1, N, n) (the A_0
+ * slot is not read); b: (2, m, d+1, N) -> dx: (2, m, d+1, n).  Workspace:
+ * md_workspace_bytes(MD_FN_SOLVE, m, N, n, d, 0, 0).  MD_ST_NONFINITE is set
+ * when dx holds an infinity or NaN.  Errors: MD_EINVAL, MD_ESHAPE,
+ * MD_ENULL, MD_EWORKSPACE. */
+int md_series_solve(int m, int N, int n, int d, const double *QR, const double *vdiag,
+                    const double *beta, const double *A, const double *b, double *dx, void *ws,
+                    size_t ws_bytes, int32_t *status, void *stream);
+
+/* One Newton step on truncated power series (Section 4): evaluate and
+ * differentiate the system at x(t), b = -f, solve A(t) dx(t) = b(t) with one
+ * QR of A_0 and the staggered substitution, then x(t) += dx(t).
+ * x: in/out planes (2, m, d+1, n) with n = sys->n; dx_norm: real planes
+ * (m, 2) (may be NULL): [max_i |dx_{d,i}|, max_{k,i} |dx_{k,i}|], the
+ * modulus of the update to the last coefficient (Section 6) and the largest
+ * update of any coefficient.  Workspace:
+ * md_workspace_bytes(MD_FN_NEWTON, m, N, n, d, M, max_deg).
+ * Errors: as md_poly_eval_diff and md_series_solve. */
+int md_newton_step(int m, int d, const md_system *sys, double *x, double *dx_norm, void *ws,
+                   size_t ws_bytes, int32_t *status, void *stream);
+
+/* Workspace size in bytes for an entry point (fn one of MD_FN_*). */
+enum { MD_FN_EVAL = 1, MD_FN_SOLVE = 2, MD_FN_NEWTON = 3 };
+size_t md_workspace_bytes(int fn, int m, int N, int n, int d, int M, int max_deg);
+
+/* One multiple-double operation per element, the units of Table 1, for
+ * operation-level checks.  Real ops read planes (m, count) and write
+ * (m, count); MD_OP_MULD multiplies by b's leading limb; complex ops read
+ * and write (2, m, count); MD_OP_CABS2 writes real planes (m, count).
+ * b is ignored by MD_OP_SQRT, MD_OP_RSQRT and MD_OP_CABS2. */
+enum {
+  MD_OP_ADD = 0, MD_OP_SUB = 1, MD_OP_MUL = 2, MD_OP_DIV = 3, MD_OP_SQRT = 4, MD_OP_RSQRT = 5,
+  MD_OP_MULD = 6, MD_OP_CADD = 7, MD_OP_CSUB = 8, MD_OP_CMUL = 9, MD_OP_CDIV = 10,
+  MD_OP_CABS2 = 11
+};
+int md_elementwise(int m, int op, int64_t count, const double *a, const double *b, double *out,
+                   void *stream);
+
+/* 2-norm sqrt(sum_j |x_j|^2) of a complex vector (Section 2's example: 64
+ * unit complex numbers have 2-norm 8).  x: planes (2, m, count), count >= 1;
+ * out: real planes (m, 1).  The sum runs over lanes in a fixed tree order. */
+int md_norm2(int m, int64_t count, const double *x, double *out, void *stream);
+
+/* Message for the last error returned on this thread ("" if none). */
+const char *md_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MDSERIES_H */

@@ -1,0 +1,278 @@
+"""Python binding of libmdseries.so: argument marshalling only.
+
+Every function here has the name of the C entry point it calls (see
+include/mdseries.h), checks the torch tensors it is given (float64 limb
+planes on the GPU, contiguous), passes their device pointers and torch's
+current HIP stream, and raises MdError when the library returns an error.
+All arithmetic runs in the library's HIP kernels; PyTorch supplies device
+memory and streams.  If the library is missing or cannot be loaded this
+module raises at import of the first call: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmdseries.so")
+
+MD_FN_EVAL, MD_FN_SOLVE, MD_FN_NEWTON = 1, 2, 3
+MD_ST_SINGULAR, MD_ST_NONFINITE = 1, 2
+OPS = {"add": 0, "sub": 1, "mul": 2, "div": 3, "sqrt": 4, "rsqrt": 5, "muld": 6,
+       "cadd": 7, "csub": 8, "cmul": 9, "cdiv": 10, "cabs2": 11}
+REAL_OPS = ("add", "sub", "mul", "div", "sqrt", "rsqrt", "muld")
+LIMBS = (1, 2, 3, 4, 5, 8, 10)
+
+
+class MdError(RuntimeError):
+    pass
+
+
+class md_system(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("n", ctypes.c_int32), ("M", ctypes.c_int32),
+                ("dc", ctypes.c_int32), ("max_deg", ctypes.c_int32),
+                ("eq_ptr", ctypes.c_void_p), ("term_ptr", ctypes.c_void_p),
+                ("factors", ctypes.c_void_p), ("coef", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise MdError(f"{LIB_PATH} is missing: build it with paper_2012_06607_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_size_t
+        L.md_series_convolve.argtypes = [i32, i32, i64, P, P, P, P]
+        L.md_poly_eval_diff.argtypes = [i32, i32, ctypes.POINTER(md_system), P, P, P, P, sz, P]
+        L.md_qr.argtypes = [i32, i32, i32, P, P, P, P, P, P]
+        L.md_series_solve.argtypes = [i32, i32, i32, i32, P, P, P, P, P, P, P, sz, P, P]
+        L.md_newton_step.argtypes = [i32, i32, ctypes.POINTER(md_system), P, P, P, sz, P, P]
+        L.md_workspace_bytes.argtypes = [i32, i32, i32, i32, i32, i32, i32]
+        L.md_workspace_bytes.restype = sz
+        L.md_elementwise.argtypes = [i32, i32, i64, P, P, P, P]
+        L.md_norm2.argtypes = [i32, i64, P, P, P]
+        L.md_last_error.restype = ctypes.c_char_p
+        for name in ("md_series_convolve", "md_poly_eval_diff", "md_qr", "md_series_solve",
+                     "md_newton_step", "md_elementwise", "md_norm2"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, name: str):
+    if rc != 0:
+        msg = lib().md_last_error().decode(errors="replace")
+        raise MdError(f"{name} returned {rc}: {msg}")
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _ptr(t: torch.Tensor | None, dtype=torch.float64):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise MdError("expected a GPU tensor")
+    if t.dtype != dtype:
+        raise MdError(f"expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise MdError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _limbs(t: torch.Tensor, complex_planes: bool = True) -> int:
+    if complex_planes:
+        if t.dim() < 2 or t.shape[0] != 2:
+            raise MdError(f"expected planes (2, m, ...), got {tuple(t.shape)}")
+        return int(t.shape[1])
+    return int(t.shape[0])
+
+
+def workspace(fn: int, m: int, N: int, n: int, d: int, M: int = 0, max_deg: int = 0,
+              device=None) -> torch.Tensor:
+    """A device workspace for an entry point (uint8 tensor)."""
+    nbytes = lib().md_workspace_bytes(fn, m, N, n, d, M, max_deg)
+    if nbytes == 0:
+        raise MdError("md_workspace_bytes: invalid sizes")
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device or "cuda")
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + nbytes]
+
+
+def validate_system(sysm):
+    """Host-side checks of the compressed structure, so that no kernel can
+    index outside the arrays it is given."""
+    ep = np.asarray(sysm.eq_ptr)
+    tp = np.asarray(sysm.term_ptr)
+    fa = np.asarray(sysm.factors)
+    if sysm.N < 1 or sysm.n < 1 or sysm.dc < 0:
+        raise MdError(f"bad system sizes N={sysm.N} n={sysm.n} dc={sysm.dc}")
+    if ep.shape != (sysm.N + 1,) or ep[0] != 0 or np.any(np.diff(ep) < 0):
+        raise MdError("eq_ptr must have N+1 non-decreasing entries from 0")
+    Mt = tp.shape[0] - 1
+    if Mt < 0 or ep[-1] != Mt or tp[0] != 0 or np.any(np.diff(tp) < 0) or tp[-1] != fa.shape[0]:
+        raise MdError("term_ptr must have M+1 non-decreasing entries from 0 to len(factors)")
+    if fa.size and (fa.min() < 0 or fa.max() >= sysm.n):
+        raise MdError("factor indices must lie in [0, n)")
+    for j in range(Mt):
+        f = fa[tp[j]:tp[j + 1]]
+        if np.any(np.diff(f) < 0):
+            raise MdError(f"factors of term {j} are not sorted")
+    if sysm.max_deg != (int(np.max(np.diff(tp))) if Mt else 0):
+        raise MdError("max_deg must be the largest number of factors of a term")
+    if sysm.coef.shape != (2, sysm.m, Mt, sysm.dc + 1):
+        raise MdError(f"coef must have shape (2, m, M, dc+1), got {sysm.coef.shape}")
+
+
+class DeviceSystem:
+    """A polynomial system (paper_2012_06607_amd.inputs.System) copied to the
+    GPU, with its md_system descriptor."""
+
+    def __init__(self, sysm, device="cuda"):
+        validate_system(sysm)
+        self.host = sysm
+        self.m = sysm.m
+        dev = torch.device(device)
+        self.eq_ptr = torch.as_tensor(np.asarray(sysm.eq_ptr, dtype=np.int32), device=dev)
+        self.term_ptr = torch.as_tensor(np.asarray(sysm.term_ptr, dtype=np.int32), device=dev)
+        fac = np.asarray(sysm.factors, dtype=np.int32)
+        self.factors = torch.as_tensor(fac if fac.size else np.zeros(1, np.int32), device=dev)
+        self.coef = torch.as_tensor(np.ascontiguousarray(sysm.coef), device=dev)
+        self.desc = md_system(sysm.N, sysm.n, sysm.M, sysm.dc, sysm.max_deg,
+                              self.eq_ptr.data_ptr(), self.term_ptr.data_ptr(),
+                              self.factors.data_ptr(), self.coef.data_ptr())
+
+    @property
+    def N(self):
+        return self.host.N
+
+    @property
+    def n(self):
+        return self.host.n
+
+
+# -----------------------------------------------------------------------------
+# entry points
+
+
+def md_series_convolve(x: torch.Tensor, y: torch.Tensor, z: torch.Tensor | None = None,
+                       stream=None) -> torch.Tensor:
+    """z = x y mod t^{d+1}; planes (2, m, count, d+1)."""
+    m = _limbs(x)
+    _, _, count, L = x.shape
+    if y.shape != x.shape:
+        raise MdError("x and y shapes differ")
+    z = torch.empty_like(x) if z is None else z
+    _check(lib().md_series_convolve(m, L - 1, count, _ptr(x), _ptr(y), _ptr(z), _stream(stream)),
+           "md_series_convolve")
+    return z
+
+
+def md_poly_eval_diff(sysd: DeviceSystem, x: torch.Tensor, f=None, A=None, ws=None,
+                      stream=None):
+    """f (2, m, d+1, N) and A (2, m, d+1, N, n) at x (2, m, d+1, n)."""
+    m = _limbs(x)
+    _, _, L, n = x.shape
+    N = sysd.N
+    f = torch.empty((2, m, L, N), dtype=torch.float64, device=x.device) if f is None else f
+    A = torch.empty((2, m, L, N, n), dtype=torch.float64, device=x.device) if A is None else A
+    if ws is None:
+        ws = workspace(MD_FN_EVAL, m, N, n, L - 1, sysd.host.M, sysd.host.max_deg, x.device)
+    _check(lib().md_poly_eval_diff(m, L - 1, ctypes.byref(sysd.desc), _ptr(x), _ptr(f), _ptr(A),
+                                   _ptr(ws, torch.uint8), ws.numel(), _stream(stream)),
+           "md_poly_eval_diff")
+    return f, A
+
+
+def md_qr(A0: torch.Tensor, status: torch.Tensor | None = None, stream=None, QR=None,
+          vdiag=None, beta=None):
+    """Householder QR of A0 (2, m, N, n) -> (QR, vdiag, beta, status)."""
+    m = _limbs(A0)
+    _, _, N, n = A0.shape
+    QR = torch.empty_like(A0) if QR is None else QR
+    vd = torch.empty((2, m, n), dtype=torch.float64, device=A0.device) if vdiag is None else vdiag
+    beta = torch.empty((m, n), dtype=torch.float64, device=A0.device) if beta is None else beta
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=A0.device)
+    _check(lib().md_qr(m, N, n, _ptr(A0), _ptr(QR), _ptr(vd), _ptr(beta), _ptr(status, torch.int32),
+                       _stream(stream)), "md_qr")
+    return QR, vd, beta, status
+
+
+def md_series_solve(QR, vdiag, beta, A, b, dx=None, ws=None, status=None, stream=None):
+    """Staggered solve of A(t) dx(t) = b(t); returns (dx, status)."""
+    m = _limbs(A)
+    _, _, L, N, n = A.shape
+    dx = torch.empty((2, m, L, n), dtype=torch.float64, device=A.device) if dx is None else dx
+    if ws is None:
+        ws = workspace(MD_FN_SOLVE, m, N, n, L - 1, 0, 0, A.device)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=A.device)
+    _check(lib().md_series_solve(m, N, n, L - 1, _ptr(QR), _ptr(vdiag), _ptr(beta), _ptr(A),
+                                 _ptr(b), _ptr(dx), _ptr(ws, torch.uint8), ws.numel(),
+                                 _ptr(status, torch.int32), _stream(stream)), "md_series_solve")
+    return dx, status
+
+
+def md_newton_step(sysd: DeviceSystem, x: torch.Tensor, dx_norm=None, ws=None, status=None,
+                   stream=None):
+    """One Newton step in place on x (2, m, d+1, n); returns (x, dx_norm (m, 2), status)."""
+    m = _limbs(x)
+    _, _, L, n = x.shape
+    if dx_norm is None:
+        dx_norm = torch.empty((m, 2), dtype=torch.float64, device=x.device)
+    if ws is None:
+        ws = workspace(MD_FN_NEWTON, m, sysd.N, n, L - 1, sysd.host.M, sysd.host.max_deg, x.device)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=x.device)
+    _check(lib().md_newton_step(m, L - 1, ctypes.byref(sysd.desc), _ptr(x), _ptr(dx_norm),
+                                _ptr(ws, torch.uint8), ws.numel(), _ptr(status, torch.int32),
+                                _stream(stream)), "md_newton_step")
+    return x, dx_norm, status
+
+
+def md_elementwise(op: str, a: torch.Tensor, b: torch.Tensor | None = None, stream=None):
+    """One multiple-double operation per element (real planes (m, count) or
+    complex planes (2, m, count))."""
+    if op in REAL_OPS:
+        m, count = a.shape
+        out = torch.empty((m, count), dtype=torch.float64, device=a.device)
+    else:
+        _, m, count = a.shape
+        out = torch.empty((m, count) if op == "cabs2" else (2, m, count), dtype=torch.float64,
+                          device=a.device)
+    _check(lib().md_elementwise(m, OPS[op], count, _ptr(a), _ptr(b), _ptr(out), _stream(stream)),
+           "md_elementwise")
+    return out
+
+
+def md_norm2(x: torch.Tensor, stream=None) -> torch.Tensor:
+    """2-norm of a complex vector (2, m, count) -> real limbs (m, 1)."""
+    m = _limbs(x)
+    count = x.shape[2]
+    out = torch.empty((m, 1), dtype=torch.float64, device=x.device)
+    _check(lib().md_norm2(m, count, _ptr(x), _ptr(out), _stream(stream)), "md_norm2")
+    return out
+
+
+def newton(sysd: DeviceSystem, x: torch.Tensor, iters: int, stream=None):
+    """iters Newton steps in place, one workspace; returns (x, list of dx_norm, status)."""
+    m = _limbs(x)
+    _, _, L, n = x.shape
+    ws = workspace(MD_FN_NEWTON, m, sysd.N, n, L - 1, sysd.host.M, sysd.host.max_deg, x.device)
+    status = torch.zeros(1, dtype=torch.int32, device=x.device)
+    norms = []
+    for _ in range(iters):
+        _, nrm, _ = md_newton_step(sysd, x, ws=ws, status=status, stream=stream)
+        norms.append(nrm)
+    return x, norms, status

@@ -1,0 +1,73 @@
+// Workspace layouts (byte offsets into the caller's device workspace).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+namespace mds {
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Evaluation: one block of series slots per term.  Slot 0 holds the value
+// c(t) P_D(t); slots 1..Dmax the derivative at factor position j (first
+// occurrences only); then the forward products P_2..P_Dmax, the backward
+// products Q_2..Q_{Dmax-1} and the cross products C_2..C_{Dmax-1}.
+struct EvalLayout {
+  int Dmax, S;
+  long E;  // complex elements in the slot planes
+  size_t bytes;
+  EvalLayout(int m, int N, int n, int d, int M, int max_deg) {
+    (void)N;
+    (void)n;
+    Dmax = max_deg;
+    S = 1 + Dmax + (Dmax > 1 ? Dmax - 1 : 0) + 2 * (Dmax > 2 ? Dmax - 2 : 0);
+    E = long(M) * S * (d + 1);
+    bytes = align256(sizeof(double) * 2 * m * (E > 0 ? E : 1));
+  }
+  __host__ __device__ int val() const { return 0; }
+  __host__ __device__ int der(int j) const { return j; }                                       // j = 1..D
+  __host__ __device__ int P(int j) const { return 1 + Dmax + (j - 2); }                         // j = 2..D
+  __host__ __device__ int Q(int j) const { return 1 + Dmax + (Dmax - 1) + (j - 2); }            // j = 2..D-1
+  __host__ __device__ int C(int j) const { return 1 + Dmax + (Dmax - 1) + (Dmax - 2) + (j - 2); }  // j = 2..D-1
+};
+
+// Staggered solve: the right hand sides r (d+1, N) and the n x N matrix
+// R^{-1} (Q^H)_{0:n} (formed in an N x N buffer).
+struct SolveLayout {
+  size_t off_r, off_G, bytes;
+  SolveLayout(int m, int N, int n, int d) {
+    (void)n;
+    off_r = 0;
+    off_G = align256(sizeof(double) * 2 * m * size_t(d + 1) * N);
+    bytes = off_G + align256(sizeof(double) * 2 * m * size_t(N) * N);
+  }
+};
+
+// Newton step: f, A, QR factors, dx, then the solve and eval workspaces.
+struct NewtonLayout {
+  size_t off_f, off_A, off_QR, off_vd, off_beta, off_dx, off_solve, off_eval, bytes;
+  NewtonLayout(int m, int N, int n, int d, int M, int max_deg) {
+    const size_t L = size_t(d + 1);
+    size_t o = 0;
+    off_f = o;
+    o += align256(sizeof(double) * 2 * m * L * N);
+    off_A = o;
+    o += align256(sizeof(double) * 2 * m * L * N * n);
+    off_QR = o;
+    o += align256(sizeof(double) * 2 * m * size_t(N) * n);
+    off_vd = o;
+    o += align256(sizeof(double) * 2 * m * size_t(n));
+    off_beta = o;
+    o += align256(sizeof(double) * m * size_t(n));
+    off_dx = o;
+    o += align256(sizeof(double) * 2 * m * L * n);
+    off_solve = o;
+    o += SolveLayout(m, N, n, d).bytes;
+    off_eval = o;
+    o += EvalLayout(m, N, n, d, M, max_deg).bytes;
+    bytes = o;
+  }
+};
+
+}  // namespace mds

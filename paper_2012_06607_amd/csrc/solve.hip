@@ -1,0 +1,206 @@
+// Staggered solve of A(t) dx(t) = b(t), the block lower triangular Toeplitz
+// system of Section 4, by forward substitution over the degrees.
+//
+// Every stage solves A_0 dx_k = r_k with the same QR factors.  Applying Q^H
+// (n reflectors in sequence) and then back substitution with R is a chain
+// of about 2n dependent steps; here that chain runs once, on the N columns
+// of the identity, giving W = R^{-1} (Q^H)_{0:n} (n x N), and every stage
+// is then the product dx_k = W r_k (least squares in the first n rows when
+// N > n).  After dx_k the later right hand sides are updated,
+// r_{k+j} -= A_j dx_k for all j = 1..d-k at once (the paper's "one job per
+// right hand side update", Section 5).
+#include "internal.hpp"
+#include "layout.hpp"
+
+namespace mds {
+
+// r = b (or -b), planes (2, m, d+1, N)
+template <int M>
+__global__ void __launch_bounds__(256) k_copy_rhs(long E, const double *__restrict__ b, bool neg,
+                                                  double *__restrict__ r) {
+  for (long e = blockIdx.x * long(blockDim.x) + threadIdx.x; e < E;
+       e += long(gridDim.x) * blockDim.x) {
+    mdc<M> z = cload<M>(b, E, e);
+    if (neg) z = c_neg<M>(z);
+    cstore<M>(r, E, e, z);
+  }
+}
+
+// W = R^{-1} (Q^H)_{0:n}, formed in G (N x N, row-major) by one workgroup:
+// G = I; G <- H_j G for j = 0..n-1 (wave-level fixed-order sums over rows);
+// then rows n-1..0: G_i <- G_i / R_ii and G_l -= R_li G_i for l < i.
+template <int M>
+__global__ void __launch_bounds__(256) k_form_pinv(int N, int n, const double *__restrict__ QR,
+                                                   const double *__restrict__ vdiag,
+                                                   const double *__restrict__ beta,
+                                                   double *__restrict__ G, int32_t *status) {
+  const long E = long(N) * n;
+  const long EG = long(N) * N;
+  const int lane = lane_id();
+  const int wave = threadIdx.x / WAVE;
+  const int nwaves = blockDim.x / WAVE;
+  for (long e = threadIdx.x; e < EG; e += blockDim.x) {
+    mdc<M> z = c_zero<M>();
+    if (e / N == e % N) z.re = md_from<M>(1.0);
+    cstore<M>(G, EG, e, z);
+  }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    const mdc<M> v0 = cload<M>(vdiag, n, j);
+    const mdr<M> bet = rload<M>(beta, n, j);
+    for (int c = wave; c < N; c += nwaves) {
+      mdc<M> w = c_zero<M>();
+      bool first = true;
+      for (int i = j + lane; i < N; i += WAVE) {
+        const mdc<M> vi = (i == j) ? v0 : cload<M>(QR, E, long(i) * n + j);
+        const mdc<M> t = c_mul<M>(c_conj<M>(vi), cload<M>(G, EG, long(i) * N + c));
+        w = first ? t : c_add<M>(w, t);
+        first = false;
+      }
+      w = seg_reduce_c<M>(w, WAVE);
+      w = shfl_c<M>(w, 0);
+      const mdc<M> bw = c_mulr<M>(w, bet);
+      for (int i = j + lane; i < N; i += WAVE) {
+        const mdc<M> vi = (i == j) ? v0 : cload<M>(QR, E, long(i) * n + j);
+        const long e = long(i) * N + c;
+        cstore<M>(G, EG, e, c_sub<M>(cload<M>(G, EG, e), c_mul<M>(bw, vi)));
+      }
+    }
+    __syncthreads();
+  }
+  int st = 0;
+  for (int i = n - 1; i >= 0; --i) {
+    const mdc<M> rii = cload<M>(QR, E, long(i) * n + i);
+    if (rii.re.v[0] == 0.0 && rii.im.v[0] == 0.0) st |= MD_ST_SINGULAR;
+    for (int c = threadIdx.x; c < N; c += blockDim.x) {
+      const long e = long(i) * N + c;
+      cstore<M>(G, EG, e, c_div<M>(cload<M>(G, EG, e), rii));
+    }
+    __syncthreads();
+    for (long q = threadIdx.x; q < long(i) * N; q += blockDim.x) {
+      const int l = int(q / N), c = int(q - long(l) * N);
+      const mdc<M> rli = cload<M>(QR, E, long(l) * n + i);
+      const long e = long(l) * N + c;
+      cstore<M>(G, EG, e, c_sub<M>(cload<M>(G, EG, e), c_mul<M>(rli, cload<M>(G, EG, long(i) * N + c))));
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && st && status) atomicOr(status, st);
+}
+
+// dx_k = W r_k: one segment of `seg` lanes per output row, lanes over the
+// N columns, fixed-order segment sum.
+template <int M>
+__global__ void __launch_bounds__(256) k_stage_dx(int k, int N, int n, int d, int seg,
+                                                  const double *__restrict__ G,
+                                                  const double *__restrict__ r,
+                                                  double *__restrict__ dx, int32_t *status) {
+  const long EG = long(N) * N;
+  const long Er = long(d + 1) * N;
+  const long Ex = long(d + 1) * n;
+  const int lane = lane_id();
+  const int rows_per_wave = WAVE / seg;
+  const int gwave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int i = gwave * rows_per_wave + lane / seg;
+  const int lis = lane & (seg - 1);
+  mdc<M> s = c_zero<M>();
+  if (i < n) {
+    bool first = true;
+    for (int c = lis; c < N; c += seg) {
+      const mdc<M> t = c_mul<M>(cload<M>(G, EG, long(i) * N + c), cload<M>(r, Er, long(k) * N + c));
+      s = first ? t : c_add<M>(s, t);
+      first = false;
+    }
+  }
+  s = seg_reduce_c<M>(s, seg);
+  if (i < n && lis == 0) {
+    cstore<M>(dx, Ex, long(k) * n + i, s);
+    if (!c_finite<M>(s) && status) atomicOr(status, MD_ST_NONFINITE);
+  }
+}
+
+// r_{k+j}[i] -= sum_l A_j[i][l] dx_k[l] for j = 1..d-k, i < N: one segment
+// of `seg` lanes per (j, i).
+template <int M>
+__global__ void __launch_bounds__(256) k_stage_update(int k, int N, int n, int d, int seg,
+                                                      const double *__restrict__ A,
+                                                      const double *__restrict__ dx,
+                                                      double *__restrict__ r) {
+  const long EA = long(d + 1) * N * n;
+  const long Er = long(d + 1) * N;
+  const long Ex = long(d + 1) * n;
+  const int lane = lane_id();
+  const int rows_per_wave = WAVE / seg;
+  const int gwave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const long row = long(gwave) * rows_per_wave + lane / seg;  // (j-1)*N + i
+  const long nrows = long(d - k) * N;
+  const int lis = lane & (seg - 1);
+  const int j = int(row / N) + 1;
+  const int i = int(row - long(j - 1) * N);
+  mdc<M> s = c_zero<M>();
+  if (row < nrows) {
+    bool first = true;
+    for (int l = lis; l < n; l += seg) {
+      const mdc<M> t = c_mul<M>(cload<M>(A, EA, (long(j) * N + i) * n + l),
+                                cload<M>(dx, Ex, long(k) * n + l));
+      s = first ? t : c_add<M>(s, t);
+      first = false;
+    }
+  }
+  s = seg_reduce_c<M>(s, seg);
+  if (row < nrows && lis == 0) {
+    const long e = long(k + j) * N + i;
+    cstore<M>(r, Er, e, c_sub<M>(cload<M>(r, Er, e), s));
+  }
+}
+
+int solve_enqueue(int m, int N, int n, int d, const double *QR, const double *vdiag,
+                  const double *beta, const double *A, const double *b, bool negate_b,
+                  double *dx, void *ws, size_t ws_bytes, int32_t *status, hipStream_t s) {
+  if (d < 0) return fail(MD_EINVAL, "md_series_solve: d=%d < 0", d);
+  if (n < 1 || N < n) return fail(MD_ESHAPE, "md_series_solve: need N >= n >= 1 (N=%d n=%d)", N, n);
+  if (!QR || !vdiag || !beta || !A || !b || !dx) return fail(MD_ENULL, "md_series_solve: null pointer");
+  if (!valid_m(m)) return dispatch_m(m, [](auto) { return MD_OK; });
+  SolveLayout lay(m, N, n, d);
+  if (!ws || ws_bytes < lay.bytes || !aligned256(ws))
+    return fail(MD_EWORKSPACE, "md_series_solve: workspace %zu bytes < %zu or misaligned",
+                ws_bytes, lay.bytes);
+  double *r = reinterpret_cast<double *>(static_cast<char *>(ws) + lay.off_r);
+  double *G = reinterpret_cast<double *>(static_cast<char *>(ws) + lay.off_G);
+  return dispatch_m(m, [&](auto Mc) {
+    constexpr int Mm = decltype(Mc)::value;
+    const long Er = long(d + 1) * N;
+    long blocks = (Er + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    k_copy_rhs<Mm><<<dim3(unsigned(blocks)), dim3(256), 0, s>>>(Er, b, negate_b, r);
+    k_form_pinv<Mm><<<dim3(1), dim3(256), 0, s>>>(N, n, QR, vdiag, beta, G, status);
+    int rc = check_launch("md_series_solve (setup)");
+    if (rc) return rc;
+    const int seg_dx = N >= WAVE ? WAVE : pow2_at_least(N);
+    const int seg_up = n >= WAVE ? WAVE : pow2_at_least(n);
+    for (int k = 0; k <= d; ++k) {
+      {
+        const long waves = (long(n) * seg_dx + WAVE - 1) / WAVE;
+        const long blk = (waves + 3) / 4;
+        k_stage_dx<Mm><<<dim3(unsigned(blk)), dim3(256), 0, s>>>(k, N, n, d, seg_dx, G, r, dx,
+                                                                  status);
+      }
+      if (k < d) {
+        const long rows = long(d - k) * N;
+        const long waves = (rows * seg_up + WAVE - 1) / WAVE;
+        const long blk = (waves + 3) / 4;
+        k_stage_update<Mm><<<dim3(unsigned(blk)), dim3(256), 0, s>>>(k, N, n, d, seg_up, A, dx, r);
+      }
+    }
+    return check_launch("md_series_solve (stages)");
+  });
+}
+
+}  // namespace mds
+
+extern "C" int md_series_solve(int m, int N, int n, int d, const double *QR, const double *vdiag,
+                               const double *beta, const double *A, const double *b, double *dx,
+                               void *ws, size_t ws_bytes, int32_t *status, void *stream) {
+  return mds::solve_enqueue(m, N, n, d, QR, vdiag, beta, A, b, false, dx, ws, ws_bytes, status,
+                            (hipStream_t)stream);
+}

@@ -146,3 +146,41 @@ def frac_of_mpf(x) -> Fraction:
     sign, man, exp, _ = mpmath.mpf(x)._mpf_
     v = Fraction(man) * Fraction(2) ** exp if man else Fraction(0)
     return -v if sign else v
+
+
+def _limb_sum_diff(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Exact (a - b) limb sums along axis 0, rounded to double at the end."""
+    m = a.shape[0]
+    flat_a = a.reshape(m, -1)
+    flat_b = b.reshape(m, -1)
+    out = np.empty(flat_a.shape[1])
+    for e in range(flat_a.shape[1]):
+        s = Fraction(0)
+        for l in range(m):
+            s += Fraction(float(flat_a[l, e])) - Fraction(float(flat_b[l, e]))
+        out[e] = float(s)
+    return out.reshape(a.shape[1:])
+
+
+def cdiff(got: np.ndarray, ref: np.ndarray) -> np.ndarray:
+    """|got - ref| per element of complex planes (2, m, ...), from exact limb
+    sums (a difference of limb-by-limb doubles would lose the tail)."""
+    dr = _limb_sum_diff(got[0], ref[0])
+    di = _limb_sum_diff(got[1], ref[1])
+    return np.hypot(dr, di)
+
+
+def rdiff(got: np.ndarray, ref: np.ndarray) -> np.ndarray:
+    """|got - ref| per element of real planes (m, ...)."""
+    return np.abs(_limb_sum_diff(got, ref))
+
+
+def planes_rel_err_per_k(got: np.ndarray, ref: np.ndarray) -> np.ndarray:
+    """Per coefficient k of series planes (2, m, d+1, ...): max_i |got - ref| /
+    max(max_i |ref_k|, 2^-40 max |ref|), all from exact limb sums."""
+    d = cdiff(got, ref)
+    r = np.hypot(ref[0].sum(axis=0), ref[1].sum(axis=0))
+    L = d.shape[0]
+    nk = np.array([r[k].max() for k in range(L)])
+    floor = max(nk.max() * 2.0**-40, 1e-300)
+    return np.array([d[k].max() / max(nk[k], floor) for k in range(L)])

@@ -1,0 +1,75 @@
+"""The C-ABI library loads and exports every entry point declared in
+include/mdseries.h; host-side argument checks return their error codes
+without touching a GPU."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mdseries.h")
+LIB = os.path.join(ROOT, "paper_2012_06607_amd", "libmdseries.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|size_t|const char \*)\s*(md_\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail(f"{LIB} not built: run paper_2012_06607_amd.build.build()")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_five_entry_points():
+    names = declared_functions()
+    for name in ("md_series_convolve", "md_poly_eval_diff", "md_qr", "md_series_solve",
+                 "md_newton_step"):
+        assert name in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_workspace_sizes(lib):
+    f = lib.md_workspace_bytes
+    f.restype = ctypes.c_size_t
+    f.argtypes = [ctypes.c_int] * 7
+    assert f(1, 4, 32, 32, 16, 512, 4) > 0
+    assert f(2, 4, 32, 32, 16, 0, 0) > 0
+    assert f(3, 2, 8, 8, 8, 80, 3) >= f(1, 2, 8, 8, 8, 80, 3) + f(2, 2, 8, 8, 8, 0, 0)
+    assert f(1, 6, 8, 8, 8, 80, 3) == 0      # m = 6 is not supported
+    assert f(9, 2, 8, 8, 8, 80, 3) == 0      # unknown entry point
+    assert f(2, 2, 8, 8, -1, 0, 0) == 0      # negative degree
+    # workspace grows linearly in the number of terms and quadratically in N
+    assert f(1, 2, 8, 8, 8, 160, 3) > f(1, 2, 8, 8, 8, 80, 3)
+    assert f(2, 2, 64, 64, 8, 0, 0) > f(2, 2, 32, 32, 8, 0, 0)
+
+
+def test_argument_errors_return_codes(lib):
+    P = ctypes.c_void_p
+    lib.md_last_error.restype = ctypes.c_char_p
+    lib.md_series_convolve.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, P, P, P, P]
+    lib.md_qr.argtypes = [ctypes.c_int] * 3 + [P] * 6
+    lib.md_elementwise.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, P, P, P, P]
+    lib.md_norm2.argtypes = [ctypes.c_int, ctypes.c_int64, P, P, P]
+    lib.md_newton_step.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, ctypes.c_size_t, P, P]
+    fake = P(4096)
+    assert lib.md_series_convolve(2, -1, 4, fake, fake, fake, None) == 1          # MD_EINVAL
+    assert lib.md_series_convolve(2, 8, 4, None, fake, fake, None) == 3           # MD_ENULL
+    assert lib.md_series_convolve(6, 8, 4, fake, fake, fake, None) == 1           # bad m
+    assert b"m=6" in lib.md_last_error()
+    assert lib.md_series_convolve(2, 8, 0, fake, fake, fake, None) == 0           # nothing to do
+    assert lib.md_series_convolve(2, 8, 0, None, None, None, None) == 0           # empty: no pointers needed
+    assert lib.md_qr(2, 3, 4, fake, fake, fake, fake, None, None) == 2            # MD_ESHAPE (N < n)
+    assert lib.md_elementwise(2, 99, 4, fake, fake, fake, None) == 1              # unknown op
+    assert lib.md_norm2(2, 0, fake, fake, None) == 1                              # empty vector
+    assert lib.md_newton_step(2, 8, None, fake, None, fake, 1 << 20, None, None) == 3

@@ -1,0 +1,340 @@
+"""GPU parity: the HIP path through the C ABI against the oracle.
+
+Single multiple-double operations, series products and evaluation /
+differentiation run the same operation sequence on both sides and must agree
+bit for bit.  QR, the staggered solve and the Newton step sum in a different
+(tree) order on the GPU, so they are compared within the per-coefficient
+tolerance 2^-(53m-8), widened by log2 of the condition number of A_0 and
+log2(k+1) for coefficient k (the paper's accuracy-loss argument, Section 4).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from exact import cdiff, planes_rel_err_per_k as rel_err_per_k, rdiff
+from paper_2012_06607_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ALL_M = (1, 2, 3, 4, 5, 8, 10)
+
+
+@pytest.fixture(scope="module")
+def B():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2012_06607_amd import binding
+    binding.lib()
+    return binding
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def tol(m, extra_bits=0.0):
+    return 2.0 ** -(53 * m - 8 - extra_bits)
+
+
+def rand_md(g, m, count):
+    out = np.zeros((m, count))
+    for e in range(count):
+        P = int(g.integers(1, 2**62)) * (1 << 700) + int.from_bytes(g.bytes(88), "little")
+        Q = 1 << (762 - int(g.integers(-30, 31)))
+        out[:, e] = I.limbs_of_ratio(-P if g.random() < 0.5 else P, Q, m)
+    return out
+
+
+# ----------------------------------------------------------------------------
+# single operations
+
+
+def test_hardware_division_and_sqrt_are_correctly_rounded(B):
+    """The quotient digits and square root seeds use the hardware double
+    division and square root; they must round like the host's IEEE ones."""
+    g = np.random.default_rng(7)
+    a = g.standard_normal((1, 200000)) * 2.0 ** g.integers(-300, 300, size=(1, 200000))
+    b = g.standard_normal((1, 200000)) * 2.0 ** g.integers(-300, 300, size=(1, 200000))
+    a[0, :100] = 2.0 ** -1070 * g.random(100)   # subnormal operands
+    assert np.array_equal(host(B.md_elementwise("div", dev(a), dev(b)))[0], a[0] / b[0])
+    assert np.array_equal(host(B.md_elementwise("sqrt", dev(np.abs(a))))[0], np.sqrt(np.abs(a[0])))
+    assert np.array_equal(host(B.md_elementwise("rsqrt", dev(np.abs(a))))[0],
+                          1.0 / np.sqrt(np.abs(a[0])))
+
+
+@pytest.mark.parametrize("m", ALL_M)
+def test_operations_bit_exact(B, m):
+    g = I.rng(950, m)
+    n = 3000
+    a, b = rand_md(g, m, n), rand_md(g, m, n)
+    b[:, :300] = -a[:, :300]                 # exact cancellation
+    b[:, 300:600] = a[:, 300:600]
+    b[1:, 600:900] = 0.0                     # b a plain double
+    a[:, 900:1000] = 0.0                     # zero operands
+    for op in ("add", "sub", "mul", "div", "muld"):
+        want = oracle.elementwise(op, a, b)
+        got = host(B.md_elementwise(op, dev(a), dev(b)))
+        same = (want == got) | (np.isnan(want) & np.isnan(got))
+        assert same.all(), (op, np.argwhere(~same)[:5])
+    pa = a * np.sign(a[0])[None, :]
+    for op in ("sqrt", "rsqrt"):
+        want = oracle.elementwise(op, pa)
+        got = host(B.md_elementwise(op, dev(pa)))
+        same = (want == got) | (np.isnan(want) & np.isnan(got))
+        assert same.all(), (op, np.argwhere(~same)[:5])
+    x = np.stack([a, b])
+    y = np.stack([b[:, ::-1], a[:, ::-1]]).copy()
+    for op in ("cadd", "csub", "cmul", "cdiv", "cabs2"):
+        want = oracle.elementwise(op, x, y)
+        got = host(B.md_elementwise(op, dev(x), dev(y)))
+        same = (want == got) | (np.isnan(want) & np.isnan(got))
+        assert same.all(), (op, np.argwhere(~same)[:5])
+
+
+@pytest.mark.parametrize("m", (2, 3, 4, 5, 8, 10))
+def test_two_norm_example(B, m):
+    """Section 2: the 2-norm of 64 unit complex numbers is 8."""
+    x = I.unit_complex(I.rng(951, m), m, 64)
+    got = host(B.md_norm2(dev(x)))[:, 0]
+    want = oracle.norm2(x)
+    assert got[0] == 8.0
+    assert abs(got[1]) <= 8.0 * tol(m)
+    assert rdiff(got[:, None], want[:, None]).max() <= 8.0 * 2.0 ** -(53 * m - 4)
+    # a ragged count above one workgroup
+    x = I.unit_complex(I.rng(952, m), m, 300)
+    got = host(B.md_norm2(dev(x)))[:, 0]
+    assert abs(got[0] - math.sqrt(300.0)) < 1e-12
+
+
+# ----------------------------------------------------------------------------
+# series products
+
+
+@pytest.mark.parametrize("m", ALL_M)
+@pytest.mark.parametrize("count,d", ((64, 32), (3, 0), (5, 1), (7, 8), (130, 17)))
+def test_convolve_bit_exact(B, m, count, d):
+    if m == 10 and count == 130:
+        pytest.skip("covered by the 64 x 32 case")
+    g = I.rng(953, m, count, d)
+    x = I.unit_complex(g, m, count, d + 1)
+    y = I.unit_complex(g, m, count, d + 1)
+    want = oracle.convolve(x, y)
+    got = host(B.md_series_convolve(dev(x), dev(y)))
+    assert np.array_equal(got, want)
+
+
+def test_convolve_empty(B):
+    x = torch.zeros((2, 2, 0, 9), dtype=torch.float64, device="cuda")
+    z = B.md_series_convolve(x, x)
+    assert z.shape == x.shape
+
+
+# ----------------------------------------------------------------------------
+# evaluation and differentiation
+
+
+def small_system(m, dc):
+    g = I.rng(954, m, dc)
+
+    def ser():
+        c = I.unit_complex(g, m, dc + 1)
+        return [(c[0, :, k], c[1, :, k]) for k in range(dc + 1)]
+    eqs = [
+        [((0, 0, 1), ser()), ((2,), ser()), ((), ser())],
+        [((0, 1, 1, 2), ser()), ((1, 1), ser()), ((0, 2), ser()), ((), ser())],
+        [((2, 2, 2), ser()), ((0, 1, 2), ser()), ((1,), ser()), ((0, 0, 0, 0, 0), ser())],
+    ]
+    return I.build_system(3, 3, m, dc, eqs)
+
+
+@pytest.mark.parametrize("m", ALL_M)
+@pytest.mark.parametrize("dc,d", ((0, 6), (3, 6), (7, 4), (1, 0)))
+def test_eval_diff_bit_exact_small(B, m, dc, d):
+    sysm = small_system(m, dc)
+    x = I.unit_complex(I.rng(955, m, d), m, d + 1, 3)
+    fw, Aw = oracle.eval_diff(sysm, x)
+    sd = B.DeviceSystem(sysm)
+    f, A = B.md_poly_eval_diff(sd, dev(x))
+    assert np.array_equal(host(f), fw)
+    assert np.array_equal(host(A), Aw)
+
+
+def test_eval_diff_bit_exact_32x32_quad_double(B):
+    """The 32 x 32 system of 16 monomials of degree <= 4 per equation, d = 16,
+    quad double, at a unit-coefficient series point: the full output."""
+    m, N, d = 4, 32, 16
+    sysm = I.eval_system((2, 0), N, N, m, 16, 4)
+    x = I.unit_series((2, 1), m, d, N)
+    fw, Aw = oracle.eval_diff(sysm, x)
+    f, A = B.md_poly_eval_diff(B.DeviceSystem(sysm), dev(x))
+    assert np.array_equal(host(f), fw)
+    assert np.array_equal(host(A), Aw)
+
+
+@pytest.mark.parametrize("m", (8, 10))
+def test_eval_diff_64x64_sampled_equations(B, m):
+    """64 x 64, 16 monomials of degree <= 4, d = 32: the oracle evaluates a
+    sample of equations on its own and the GPU rows must match bit for bit."""
+    N, d = 64, 32
+    sysm = I.eval_system((3, 0), N, N, m, 16, 4)
+    x = I.unit_series((3, 1), m, d, N)
+    f, A = B.md_poly_eval_diff(B.DeviceSystem(sysm), dev(x))
+    f, A = host(f), host(A)
+    for i in (0, 29, 63):
+        sub = I.build_system(1, N, m, sysm.dc, [[
+            (fac, [(sysm.coef[0, :, j, k], sysm.coef[1, :, j, k]) for k in range(sysm.dc + 1)])
+            for j, fac in sysm.terms(i)]])
+        fw, Aw = oracle.eval_diff(sub, x)
+        assert np.array_equal(f[:, :, :, i], fw[:, :, :, 0])
+        assert np.array_equal(A[:, :, :, i, :], Aw[:, :, :, 0, :])
+
+
+# ----------------------------------------------------------------------------
+# QR and the staggered solve
+
+
+def compare_qr(got, want, m, cond):
+    QRg, vdg, bg = got
+    QRw, vdw, bw = want
+    N, n = QRw.shape[2:]
+    scale = np.abs(QRw[0, 0] + 1j * QRw[1, 0]).max()
+    iu = np.triu_indices(n)
+    dR = cdiff(QRg[:, :, :n], QRw[:, :, :n])[iu]
+    assert dR.max() <= tol(m, math.log2(cond) + 4) * scale
+    assert cdiff(vdg, vdw).max() <= tol(m, math.log2(cond) + 4) * scale
+    assert (rdiff(bg, bw) / np.abs(bw[0])).max() <= tol(m, math.log2(cond) + 4)
+
+
+@pytest.mark.parametrize("m", (2, 4, 8))
+@pytest.mark.parametrize("shape", ((32, 32), (1, 1), (3, 2), (70, 24)))
+def test_qr_within_tolerance(B, m, shape):
+    N, n = shape
+    A0 = I.unit_complex(I.rng(956, m, N, n), m, N, n)
+    QRw, vdw, bw, stw = oracle.qr(A0)
+    QR, vd, beta, st = B.md_qr(dev(A0))
+    assert int(host(st)[0]) == stw == 0
+    s = np.linalg.svd(A0[0, 0] + 1j * A0[1, 0], compute_uv=False)
+    compare_qr((host(QR), host(vd), host(beta)), (QRw, vdw, bw), m, s[0] / s[-1])
+
+
+def test_qr_flags_singular_column(B):
+    m = 2
+    A0 = I.unit_complex(I.rng(957), m, 5, 5)
+    A0[:, :, :, 2] = 0.0
+    _, _, beta, st = B.md_qr(dev(A0))
+    assert int(host(st)[0]) & B.MD_ST_SINGULAR
+    assert np.all(host(beta)[:, 2] == 0.0)
+
+
+def solve_case(B, m, N, n, d, key):
+    if N == n:
+        A, b = I.toeplitz_system(key, n, d, m)
+    else:
+        g = I.rng(*key)
+        A = I.unit_complex(g, m, d + 1, N, n)
+        b = I.unit_complex(g, m, d + 1, N)
+    dxw, stw = oracle.solve_toeplitz(A, b)
+    QR, vd, beta, st = B.md_qr(dev(A[:, :, 0]))
+    dx, st2 = B.md_series_solve(QR, vd, beta, dev(A), dev(b))
+    assert int(host(st)[0]) == 0 and int(host(st2)[0]) == 0 and stw == 0
+    A0 = A[0, 0, 0] + 1j * A[1, 0, 0]
+    s = np.linalg.svd(A0, compute_uv=False)
+    e = rel_err_per_k(host(dx), dxw)
+    for k in range(d + 1):
+        assert e[k] <= tol(m, math.log2(s[0] / s[-1]) + math.log2(k + 1) + 2), (k, e)
+
+
+@pytest.mark.parametrize("m", (2, 4))
+def test_solve_32_quad_double_config(B, m):
+    """n = 32, d = 16, A_0 = U diag U^H with condition number 1e3."""
+    solve_case(B, m, 32, 32, 16, (2, 32))
+
+
+@pytest.mark.parametrize("m,N,n,d", ((2, 1, 1, 0), (3, 5, 5, 3), (5, 9, 9, 2), (2, 70, 70, 3),
+                                     (4, 12, 7, 4)))
+def test_solve_edge_shapes(B, m, N, n, d):
+    solve_case(B, m, N, n, d, (960, N, n, d))
+
+
+@pytest.mark.parametrize("m", (8, 10))
+def test_solve_64_octo_deca_double(B, m):
+    """n = 64, d = 32 at octo and deca double (the oracle takes ~10 s)."""
+    solve_case(B, m, 64, 64, 32, (2, 64))
+
+
+# ----------------------------------------------------------------------------
+# Newton steps
+
+
+def newton_compare(B, sysm, x, iters, m):
+    sd = B.DeviceSystem(sysm)
+    xg = dev(x)
+    cond = sysm.meta.get("cond_A0_double", 10.0)
+    for it in range(iters):
+        xw, nrmw, stw = oracle.newton_step(sysm, x)
+        _, nrm, st = B.md_newton_step(sd, xg)
+        xh = host(xg)
+        e = rel_err_per_k(xh, xw)
+        for k in range(xw.shape[2]):
+            assert e[k] <= tol(m, math.log2(cond) + math.log2(k + 1) + 4), (it, k, e)
+        assert int(host(st)[0]) == stw == 0
+        nh = host(nrm)
+        assert abs(nh[0, 0] - nrmw[0, 0]) <= 1e-6 * nrmw[0, 0] + 2.0 ** -(53 * m - 12)
+        x = xw  # continue both from the oracle's iterate
+        xg = dev(x)
+    return x, nh
+
+
+def test_newton_plain_double_double_config(B):
+    """n = 8, 8 monomials of degree <= 3 per equation, d = 8, 8 iterations."""
+    m, d = 2, 8
+    sysm, x0 = I.newton_system((0, 0), 8, m)
+    x, nrm = newton_compare(B, sysm, I.series_start(x0, d), 8, m)
+    # converged: the last update is at the precision's level relative to x_d
+    xd = np.abs(x[0, 0, d] + 1j * x[1, 0, d]).max()
+    assert nrm[0, 0] <= 2.0 ** -(53 * m - 16) * max(1.0, xd)
+
+
+@pytest.mark.parametrize("m", (2, 4))
+def test_circle_example(B, m):
+    sysm, x = I.circle_system(m, 8)
+    newton_compare(B, sysm, x, 6, m)
+
+
+def test_sqrt_series_exact(B):
+    m, d = 4, 16
+    sysm, x = I.sqrt_system(m, d)
+    xg = dev(x)
+    B.newton(B.DeviceSystem(sysm), xg, 6)
+    xw, _, _ = oracle.newton(sysm, x, 6)
+    assert np.array_equal(host(xg), xw)  # dyadic coefficients: both exact
+
+
+def test_newton_deterministic(B):
+    m, d = 4, 12
+    sysm, x0 = I.newton_system((5, 0), 12, m)
+    sd = B.DeviceSystem(sysm)
+    outs = []
+    for _ in range(2):
+        xg = dev(I.series_start(x0, d))
+        B.newton(sd, xg, 3)
+        outs.append(host(xg))
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_newton_nonfinite_flag(B):
+    m, d = 2, 4
+    sysm, x0 = I.newton_system((6, 0), 4, m)
+    x = I.series_start(x0, d)
+    x[0, 0, 0, 1] = np.nan
+    _, _, st = B.md_newton_step(B.DeviceSystem(sysm), dev(x))
+    assert int(host(st)[0]) & B.MD_ST_NONFINITE
