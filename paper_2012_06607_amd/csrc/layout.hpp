@@ -32,15 +32,14 @@ struct EvalLayout {
   __host__ __device__ int C(int j) const { return 1 + Dmax + (Dmax - 1) + (Dmax - 2) + (j - 2); }  // j = 2..D-1
 };
 
-// Staggered solve: the right hand sides r (d+1, N) and the n x N matrix
-// R^{-1} (Q^H)_{0:n} (formed in an N x N buffer).
+// Staggered solve: the right hand sides r (d+1, N), the n x N matrix
+// W = R^{-1} (Q^H)_{0:n}, then 1/R_ii (n).
 struct SolveLayout {
   size_t off_r, off_G, bytes;
   SolveLayout(int m, int N, int n, int d) {
-    (void)n;
     off_r = 0;
     off_G = align256(sizeof(double) * 2 * m * size_t(d + 1) * N);
-    bytes = off_G + align256(sizeof(double) * 2 * m * size_t(N) * N);
+    bytes = off_G + align256(sizeof(double) * 2 * m * (size_t(n) * N + n));
   }
 };
 

@@ -26,66 +26,95 @@ __global__ void __launch_bounds__(256) k_copy_rhs(long E, const double *__restri
   }
 }
 
-// W = R^{-1} (Q^H)_{0:n}, formed in G (N x N, row-major) by one workgroup:
-// G = I; G <- H_j G for j = 0..n-1 (wave-level fixed-order sums over rows);
-// then rows n-1..0: G_i <- G_i / R_ii and G_l -= R_li G_i for l < i.
+// 1 / R_ii for i < n (one thread each), so that the back substitution
+// multiplies instead of dividing.
 template <int M>
-__global__ void __launch_bounds__(256) k_form_pinv(int N, int n, const double *__restrict__ QR,
+__global__ void __launch_bounds__(64) k_inv_diag(int N, int n, const double *__restrict__ QR,
+                                                 double *__restrict__ invd, int32_t *status) {
+  const long E = long(N) * n;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const mdc<M> rii = cload<M>(QR, E, long(i) * n + i);
+    if (rii.re.v[0] == 0.0 && rii.im.v[0] == 0.0 && status) atomicOr(status, MD_ST_SINGULAR);
+    mdc<M> one = c_zero<M>();
+    one.re = md_from<M>(1.0);
+    cstore<M>(invd, n, i, c_div<M>(one, rii));
+  }
+}
+
+// W = R^{-1} (Q^H)_{0:n}, column by column: column c of the identity is held
+// in registers by a segment of `seg` lanes (lane l keeps rows l, l+seg, ...,
+// at most RPL rows), the n reflectors are applied in order
+// (w = v^H g by a fixed-order segment sum, g -= beta w v), then the back
+// substitution R W_c = g_{0:n} runs with the row owner multiplying by
+// 1/R_ii and broadcasting.  W: row-major n x N (plane stride n*N).
+template <int M, int RPL>
+__global__ void __launch_bounds__(256) k_pinv_cols(int N, int n, int seg,
+                                                   const double *__restrict__ QR,
                                                    const double *__restrict__ vdiag,
                                                    const double *__restrict__ beta,
-                                                   double *__restrict__ G, int32_t *status) {
+                                                   const double *__restrict__ invd,
+                                                   double *__restrict__ W) {
   const long E = long(N) * n;
-  const long EG = long(N) * N;
+  const long EW = long(n) * N;
   const int lane = lane_id();
-  const int wave = threadIdx.x / WAVE;
-  const int nwaves = blockDim.x / WAVE;
-  for (long e = threadIdx.x; e < EG; e += blockDim.x) {
-    mdc<M> z = c_zero<M>();
-    if (e / N == e % N) z.re = md_from<M>(1.0);
-    cstore<M>(G, EG, e, z);
+  const int lis = lane & (seg - 1);
+  const int segs_per_wave = WAVE / seg;
+  const int gwave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int c = gwave * segs_per_wave + lane / seg;
+  const bool live = c < N;
+  mdc<M> g[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    g[r] = c_zero<M>();
+    if (live && lis + r * seg == c) g[r].re = md_from<M>(1.0);
   }
-  __syncthreads();
   for (int j = 0; j < n; ++j) {
     const mdc<M> v0 = cload<M>(vdiag, n, j);
     const mdr<M> bet = rload<M>(beta, n, j);
-    for (int c = wave; c < N; c += nwaves) {
-      mdc<M> w = c_zero<M>();
-      bool first = true;
-      for (int i = j + lane; i < N; i += WAVE) {
-        const mdc<M> vi = (i == j) ? v0 : cload<M>(QR, E, long(i) * n + j);
-        const mdc<M> t = c_mul<M>(c_conj<M>(vi), cload<M>(G, EG, long(i) * N + c));
+    mdc<M> vi[RPL];
+    mdc<M> w = c_zero<M>();
+    bool first = true;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int i = lis + r * seg;
+      vi[r] = c_zero<M>();
+      if (i >= j && i < N) {
+        vi[r] = (i == j) ? v0 : cload<M>(QR, E, long(i) * n + j);
+        const mdc<M> t = c_mul<M>(c_conj<M>(vi[r]), g[r]);
         w = first ? t : c_add<M>(w, t);
         first = false;
       }
-      w = seg_reduce_c<M>(w, WAVE);
-      w = shfl_c<M>(w, 0);
-      const mdc<M> bw = c_mulr<M>(w, bet);
-      for (int i = j + lane; i < N; i += WAVE) {
-        const mdc<M> vi = (i == j) ? v0 : cload<M>(QR, E, long(i) * n + j);
-        const long e = long(i) * N + c;
-        cstore<M>(G, EG, e, c_sub<M>(cload<M>(G, EG, e), c_mul<M>(bw, vi)));
-      }
     }
-    __syncthreads();
+    w = seg_reduce_c<M>(w, seg);
+    w = shfl_c<M>(w, lane & ~(seg - 1));
+    const mdc<M> bw = c_mulr<M>(w, bet);
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int i = lis + r * seg;
+      if (i >= j && i < N) g[r] = c_sub<M>(g[r], c_mul<M>(bw, vi[r]));
+    }
   }
-  int st = 0;
   for (int i = n - 1; i >= 0; --i) {
-    const mdc<M> rii = cload<M>(QR, E, long(i) * n + i);
-    if (rii.re.v[0] == 0.0 && rii.im.v[0] == 0.0) st |= MD_ST_SINGULAR;
-    for (int c = threadIdx.x; c < N; c += blockDim.x) {
-      const long e = long(i) * N + c;
-      cstore<M>(G, EG, e, c_div<M>(cload<M>(G, EG, e), rii));
+    const int owner = i & (seg - 1), ro = i / seg;
+    mdc<M> xi = c_zero<M>();
+#pragma unroll
+    for (int r = 0; r < RPL; ++r)
+      if (r == ro && lis == owner) xi = c_mul<M>(g[r], cload<M>(invd, n, i));
+    xi = shfl_c<M>(xi, (lane & ~(seg - 1)) + owner);
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int l = lis + r * seg;
+      if (l == i) g[r] = xi;
+      else if (l < i) g[r] = c_sub<M>(g[r], c_mul<M>(cload<M>(QR, E, long(l) * n + i), xi));
     }
-    __syncthreads();
-    for (long q = threadIdx.x; q < long(i) * N; q += blockDim.x) {
-      const int l = int(q / N), c = int(q - long(l) * N);
-      const mdc<M> rli = cload<M>(QR, E, long(l) * n + i);
-      const long e = long(l) * N + c;
-      cstore<M>(G, EG, e, c_sub<M>(cload<M>(G, EG, e), c_mul<M>(rli, cload<M>(G, EG, long(i) * N + c))));
-    }
-    __syncthreads();
   }
-  if (threadIdx.x == 0 && st && status) atomicOr(status, st);
+  if (live) {
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int i = lis + r * seg;
+      if (i < n) cstore<M>(W, EW, long(i) * N + c, g[r]);
+    }
+  }
 }
 
 // dx_k = W r_k: one segment of `seg` lanes per output row, lanes over the
@@ -95,7 +124,7 @@ __global__ void __launch_bounds__(256) k_stage_dx(int k, int N, int n, int d, in
                                                   const double *__restrict__ G,
                                                   const double *__restrict__ r,
                                                   double *__restrict__ dx, int32_t *status) {
-  const long EG = long(N) * N;
+  const long EG = long(n) * N;
   const long Er = long(d + 1) * N;
   const long Ex = long(d + 1) * n;
   const int lane = lane_id();
@@ -159,6 +188,7 @@ int solve_enqueue(int m, int N, int n, int d, const double *QR, const double *vd
                   double *dx, void *ws, size_t ws_bytes, int32_t *status, hipStream_t s) {
   if (d < 0) return fail(MD_EINVAL, "md_series_solve: d=%d < 0", d);
   if (n < 1 || N < n) return fail(MD_ESHAPE, "md_series_solve: need N >= n >= 1 (N=%d n=%d)", N, n);
+  if (N > 256) return fail(MD_ESHAPE, "md_series_solve: N=%d above 256", N);
   if (!QR || !vdiag || !beta || !A || !b || !dx) return fail(MD_ENULL, "md_series_solve: null pointer");
   if (!valid_m(m)) return dispatch_m(m, [](auto) { return MD_OK; });
   SolveLayout lay(m, N, n, d);
@@ -173,7 +203,22 @@ int solve_enqueue(int m, int N, int n, int d, const double *QR, const double *vd
     long blocks = (Er + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     k_copy_rhs<Mm><<<dim3(unsigned(blocks)), dim3(256), 0, s>>>(Er, b, negate_b, r);
-    k_form_pinv<Mm><<<dim3(1), dim3(256), 0, s>>>(N, n, QR, vdiag, beta, G, status);
+    double *invd = G + size_t(2) * Mm * n * N;
+    k_inv_diag<Mm><<<dim3((n + 63) / 64), dim3(64), 0, s>>>(N, n, QR, invd, status);
+    {
+      const int seg = N >= WAVE ? WAVE : pow2_at_least(N);
+      const long waves = (long(N) * seg + WAVE - 1) / WAVE;
+      const unsigned blk = unsigned((waves + 3) / 4);
+      const int rpl = (N + seg - 1) / seg;
+      if (rpl == 1)
+        k_pinv_cols<Mm, 1><<<dim3(blk), dim3(256), 0, s>>>(N, n, seg, QR, vdiag, beta, invd, G);
+      else if (rpl == 2)
+        k_pinv_cols<Mm, 2><<<dim3(blk), dim3(256), 0, s>>>(N, n, seg, QR, vdiag, beta, invd, G);
+      else if (rpl <= 4)
+        k_pinv_cols<Mm, 4><<<dim3(blk), dim3(256), 0, s>>>(N, n, seg, QR, vdiag, beta, invd, G);
+      else
+        return fail(MD_ESHAPE, "md_series_solve: N=%d above 256", N);
+    }
     int rc = check_launch("md_series_solve (setup)");
     if (rc) return rc;
     const int seg_dx = N >= WAVE ? WAVE : pow2_at_least(N);

@@ -1,11 +1,13 @@
 """GPU parity: the HIP path through the C ABI against the oracle.
 
-Single multiple-double operations, series products and evaluation /
-differentiation run the same operation sequence on both sides and must agree
-bit for bit.  QR, the staggered solve and the Newton step sum in a different
-(tree) order on the GPU, so they are compared within the per-coefficient
-tolerance 2^-(53m-8), widened by log2 of the condition number of A_0 and
-log2(k+1) for coefficient k (the paper's accuracy-loss argument, Section 4).
+Single multiple-double operations and the series product entry point run
+the same operation sequence on both sides and must agree bit for bit.  The
+evaluation kernel splits each coefficient's products over lanes, and QR,
+the staggered solve and the Newton step sum in a different (tree) order on
+the GPU, so they are compared within the per-coefficient tolerance
+2^-(53m-8), widened for the solves by log2 of the condition number of A_0
+and log2(k+1) for coefficient k (the paper's accuracy-loss argument,
+Section 4).
 """
 from __future__ import annotations
 
@@ -156,19 +158,26 @@ def small_system(m, dc):
     return I.build_system(3, 3, m, dc, eqs)
 
 
+def eval_close(got, want, m, bits=4):
+    """Per coefficient: |gpu - oracle| <= 2^-(53m - 8 - bits) of the
+    coefficient's largest entry (products summed in another order)."""
+    e = rel_err_per_k(got, want)
+    assert np.all(e <= tol(m, bits)), e
+
+
 @pytest.mark.parametrize("m", ALL_M)
 @pytest.mark.parametrize("dc,d", ((0, 6), (3, 6), (7, 4), (1, 0)))
-def test_eval_diff_bit_exact_small(B, m, dc, d):
+def test_eval_diff_small(B, m, dc, d):
     sysm = small_system(m, dc)
     x = I.unit_complex(I.rng(955, m, d), m, d + 1, 3)
     fw, Aw = oracle.eval_diff(sysm, x)
     sd = B.DeviceSystem(sysm)
     f, A = B.md_poly_eval_diff(sd, dev(x))
-    assert np.array_equal(host(f), fw)
-    assert np.array_equal(host(A), Aw)
+    eval_close(host(f), fw, m)
+    eval_close(host(A), Aw, m)
 
 
-def test_eval_diff_bit_exact_32x32_quad_double(B):
+def test_eval_diff_32x32_quad_double(B):
     """The 32 x 32 system of 16 monomials of degree <= 4 per equation, d = 16,
     quad double, at a unit-coefficient series point: the full output."""
     m, N, d = 4, 32, 16
@@ -176,14 +185,14 @@ def test_eval_diff_bit_exact_32x32_quad_double(B):
     x = I.unit_series((2, 1), m, d, N)
     fw, Aw = oracle.eval_diff(sysm, x)
     f, A = B.md_poly_eval_diff(B.DeviceSystem(sysm), dev(x))
-    assert np.array_equal(host(f), fw)
-    assert np.array_equal(host(A), Aw)
+    eval_close(host(f), fw, m)
+    eval_close(host(A), Aw, m)
 
 
 @pytest.mark.parametrize("m", (8, 10))
 def test_eval_diff_64x64_sampled_equations(B, m):
     """64 x 64, 16 monomials of degree <= 4, d = 32: the oracle evaluates a
-    sample of equations on its own and the GPU rows must match bit for bit."""
+    sample of equations on its own and the GPU rows must agree."""
     N, d = 64, 32
     sysm = I.eval_system((3, 0), N, N, m, 16, 4)
     x = I.unit_series((3, 1), m, d, N)
@@ -194,8 +203,8 @@ def test_eval_diff_64x64_sampled_equations(B, m):
             (fac, [(sysm.coef[0, :, j, k], sysm.coef[1, :, j, k]) for k in range(sysm.dc + 1)])
             for j, fac in sysm.terms(i)]])
         fw, Aw = oracle.eval_diff(sub, x)
-        assert np.array_equal(f[:, :, :, i], fw[:, :, :, 0])
-        assert np.array_equal(A[:, :, :, i, :], Aw[:, :, :, 0, :])
+        eval_close(np.ascontiguousarray(f[:, :, :, i:i + 1]), fw, m)
+        eval_close(np.ascontiguousarray(A[:, :, :, i:i + 1, :]), Aw, m)
 
 
 # ----------------------------------------------------------------------------
@@ -288,7 +297,10 @@ def newton_compare(B, sysm, x, iters, m):
             assert e[k] <= tol(m, math.log2(cond) + math.log2(k + 1) + 4), (it, k, e)
         assert int(host(st)[0]) == stw == 0
         nh = host(nrm)
-        assert abs(nh[0, 0] - nrmw[0, 0]) <= 1e-6 * nrmw[0, 0] + 2.0 ** -(53 * m - 12)
+        # near convergence the update is rounding noise: compare at the level
+        # of the precision relative to the last coefficient
+        xd = max(1.0, np.abs(xw[0, 0, -1] + 1j * xw[1, 0, -1]).max())
+        assert abs(nh[0, 0] - nrmw[0, 0]) <= 1e-6 * nrmw[0, 0] + 2.0 ** -(53 * m - 16) * xd
         x = xw  # continue both from the oracle's iterate
         xg = dev(x)
     return x, nh
