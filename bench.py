@@ -44,6 +44,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall time budget of the CPU oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-paths measurement (1024 paths, one persistent launch)")
+    ap.add_argument("--batch-paths", type=int, default=1024)
+    ap.add_argument("--batch-reps", type=int, default=5)
     return ap.parse_args()
 
 
@@ -73,6 +77,86 @@ def cpu_baseline(sysm, x, A, b, budget_s: float) -> dict:
     return {"value": steps / el, "unit": "steps/s", "cores": 1, "kind": "oracle",
             "sample": f"{steps} full steps of the same workload on one host thread "
                       f"({el:.1f} s, gcc -O2 C oracle)"}
+
+
+def batched_measure(args, B, OC):
+    """1024 independent paths (n in {8,...,64}, d in 8..32, half double double,
+    half quad double, systems of 8 monomials of degree <= 3 per equation with
+    a root at t = 0), 4 Newton steps each: one persistent launch captured in a
+    graph and replayed, against the per-path launch loop on the same GPU."""
+    import numpy as np
+    import torch
+    from paper_2012_06607_amd import inputs as I
+    iters = 4
+    specs = I.batch_specs((4, 0), args.batch_paths)
+    paths = []
+    for sp in specs:
+        sysm, x0 = I.newton_system((4, sp.path), sp.n, sp.m)
+        paths.append((sysm, I.series_start(x0, sp.d)))
+    ops = sum(iters * OC.newton_step(sysm, x.shape[2] - 1, sysm.m).table_ops(sysm.m)
+              for sysm, x in paths)
+    ops_qd = sum(iters * OC.newton_step(sysm, x.shape[2] - 1, sysm.m).table_ops(sysm.m)
+                 for sysm, x in paths if sysm.m == 4)
+    batch = B.BatchedPaths(paths)
+    stream = torch.cuda.current_stream()
+    B.md_newton_batch(batch, iters)           # warm up, then capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        B.md_newton_batch(batch, iters)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(args.batch_reps):
+        batch.reset(paths)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        g.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = float(np.median(times))
+    st = int(batch.status.max().item())
+    # the per-path launch loop on the same paths
+    sds = [B.DeviceSystem(sysm) for sysm, _ in paths]
+    xs = [torch.as_tensor(x, device="cuda") for _, x in paths]
+    wss = [B.workspace(B.MD_FN_NEWTON, sysm.m, sysm.N, sysm.n, x.shape[2] - 1, sysm.M,
+                       sysm.max_deg) for sysm, x in paths]
+    stat = torch.zeros(1, dtype=torch.int32, device="cuda")
+    nrm = [torch.empty((sysm.m, 2), dtype=torch.float64, device="cuda") for sysm, _ in paths]
+
+    def loop():
+        for p in range(len(paths)):
+            for _ in range(iters):
+                B.md_newton_step(sds[p], xs[p], nrm[p], wss[p], stat, stream)
+    loop()
+    torch.cuda.synchronize()
+    for p, (_, x) in enumerate(paths):
+        xs[p].copy_(torch.as_tensor(x))
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    loop()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_loop = e0.elapsed_time(e1)
+    same = all(torch.equal(xs[p], batch.x(p)) for p in range(len(paths)))
+    steps = len(paths) * iters
+    peak = OC.FP64_VECTOR_PEAK
+    return {
+        "workload": f"{len(paths)} paths, n in 8..64 step 8, d in 8..32, half dd / half qd, "
+                    f"8 monomials of degree <= 3 per equation, {iters} Newton steps each",
+        "steps_per_s": round(steps / (ms * 1e-3), 2),
+        "ms_per_launch": round(ms, 3),
+        "table_ops_per_launch": ops,
+        "pct_fp64_vector_peak": round(100.0 * ops / (ms * 1e-3) / peak, 3),
+        "qd_share_of_ops": round(ops_qd / ops, 4),
+        "per_path_loop_ms": round(ms_loop, 3),
+        "speedup_vs_per_path_loop": round(ms_loop / ms, 2),
+        "bitwise_equal_to_per_path": bool(same),
+        "graph_replays": args.batch_reps,
+        "status": st,
+    }
 
 
 def main():
@@ -174,6 +258,8 @@ def main():
                               "multiple-double operations per launch / mean launch time"},
         "status": st,
     }
+    if not args.no_batched:
+        line["batched"] = batched_measure(args, B, OC)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(sysm, x_h, A_h, b_h, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -57,8 +57,9 @@ enum {
 };
 
 enum {
-  MD_ST_SINGULAR = 1, /* a Householder column or a diagonal of R is zero */
-  MD_ST_NONFINITE = 2 /* an infinity or NaN reached a result */
+  MD_ST_SINGULAR = 1,  /* a Householder column or a diagonal of R is zero */
+  MD_ST_NONFINITE = 2, /* an infinity or NaN reached a result */
+  MD_ST_BADPATH = 4    /* md_newton_batch: a path's sizes or precision are not supported */
 };
 
 /* Polynomial system f = (f_1..f_N) in x = (x_1..x_n), N >= n, whose terms
@@ -167,6 +168,53 @@ int md_elementwise(int m, int op, int64_t count, const double *a, const double *
  * unit complex numbers have 2-norm 8).  x: planes (2, m, count), count >= 1;
  * out: real planes (m, 1).  The sum runs over lanes in a fixed tree order. */
 int md_norm2(int m, int64_t count, const double *x, double *out, void *stream);
+
+/* ---- batched paths (extension beyond the five entry points) -------------
+ *
+ * Many independent solution paths in one persistent launch: the paper's job
+ * queue (Section 5, Figure 1) with workgroups as workers and one device
+ * atomic as the counter; a job is a whole path, `iters` Newton steps run by
+ * one workgroup with barriers between the stages.  Every stage runs the
+ * same segment-level code as md_newton_step, so a batched path gives the
+ * same bits as md_newton_step applied `iters` times to that path.
+ *
+ * One path, in a device array of md_path (all offsets are element offsets):
+ *   m in 1..4 (the batched kernel carries double to quad double), N == n or
+ *   N > n with N <= 64, d >= 0;
+ *   eq_ptr, term_ptr, factors: offsets into `ints` (int32) of the path's
+ *   system structure, laid out as in md_system (M terms, max_deg factors at
+ *   most, coefficient degree dc);
+ *   coef: offset into `reals` of the coefficient planes (2, m, M, dc+1);
+ *   x: offset into `reals` of the path's series (2, m, d+1, n), in/out;
+ *   dx_norm: offset into `reals` of real planes (m, 2) written after the last
+ *   step (as md_newton_step's dx_norm);
+ *   ws: offset into `ws` (doubles, a multiple of 32) of the path's private
+ *   workspace of md_workspace_bytes(MD_FN_NEWTON, m, N, n, d, M, max_deg)
+ *   bytes. */
+typedef struct md_path {
+  int32_t m, N, n, d;
+  int32_t M, dc, max_deg, reserved;
+  int64_t eq_ptr, term_ptr, factors;
+  int64_t coef, x, dx_norm;
+  int64_t ws;
+} md_path;
+
+/* LDS bytes the batched kernel needs for its evaluation stage. */
+size_t md_batch_lds_bytes(int max_m, int max_d, int max_deg, int eval_waves);
+
+/* Runs `iters` Newton steps on each of `npaths` paths.  paths: device
+ * md_path[npaths]; order: device int32[npaths], the order in which jobs are
+ * handed out (a permutation of 0..npaths-1); counter: a device int32 used as the job counter
+ * (reset by the call itself, on the stream, so the call can be captured in a
+ * graph and replayed); status: device
+ * int32[npaths], MD_ST_* bits per path, cleared by the caller; max_m, max_d,
+ * max_deg: maxima over the paths (host values, they size the LDS); grid:
+ * the number of resident workgroups (256 threads each); eval_waves (1..4):
+ * waves per workgroup that evaluate terms.  Errors: MD_EINVAL, MD_ENULL,
+ * MD_ESHAPE (LDS above 64 KiB), MD_EHIP. */
+int md_newton_batch(int npaths, const md_path *paths, const int32_t *order, const int32_t *ints,
+                    double *reals, double *ws, int iters, int32_t *counter, int32_t *status,
+                    int max_m, int max_d, int max_deg, int grid, int eval_waves, void *stream);
 
 /* Message for the last error returned on this thread ("" if none). */
 const char *md_last_error(void);

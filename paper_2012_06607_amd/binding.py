@@ -276,3 +276,120 @@ def newton(sysd: DeviceSystem, x: torch.Tensor, iters: int, stream=None):
         _, nrm, _ = md_newton_step(sysd, x, ws=ws, status=status, stream=stream)
         norms.append(nrm)
     return x, norms, status
+
+
+# -----------------------------------------------------------------------------
+# batched paths
+
+MD_PATH_DTYPE = np.dtype([("m", "<i4"), ("N", "<i4"), ("n", "<i4"), ("d", "<i4"),
+                          ("M", "<i4"), ("dc", "<i4"), ("max_deg", "<i4"), ("reserved", "<i4"),
+                          ("eq_ptr", "<i8"), ("term_ptr", "<i8"), ("factors", "<i8"),
+                          ("coef", "<i8"), ("x", "<i8"), ("dx_norm", "<i8"), ("ws", "<i8")])
+assert MD_PATH_DTYPE.itemsize == 88
+
+
+class BatchedPaths:
+    """Device arenas for md_newton_batch: every path's system structure (one
+    int32 arena), coefficients, series and update norms (one float64 arena),
+    and private workspaces (one float64 arena, 256-byte aligned slices).
+    `paths` is a list of (System, x planes (2, m, d+1, n)); `order` (job
+    order) defaults to longest first by the analytic operation count."""
+
+    def __init__(self, paths, device="cuda", order=None):
+        from . import opcount as OC
+        ints, reals = [], []
+        n_int, n_real, n_ws = 0, 0, 0
+        table = np.zeros(len(paths), dtype=MD_PATH_DTYPE)
+        cost = np.zeros(len(paths))
+        self.meta = []
+        for p, (sysm, x) in enumerate(paths):
+            validate_system(sysm)
+            m = sysm.m
+            d = x.shape[2] - 1
+            if x.shape != (2, m, d + 1, sysm.n):
+                raise MdError(f"path {p}: x must have shape (2, m, d+1, n)")
+            t = table[p]
+            t["m"], t["N"], t["n"], t["d"] = m, sysm.N, sysm.n, d
+            t["M"], t["dc"], t["max_deg"] = sysm.M, sysm.dc, sysm.max_deg
+            for name in ("eq_ptr", "term_ptr", "factors"):
+                arr = np.asarray(getattr(sysm, name), dtype=np.int32)
+                t[name] = n_int
+                ints.append(arr)
+                n_int += arr.size
+            for name, arr in (("coef", sysm.coef), ("x", x), ("dx_norm", np.zeros((m, 2)))):
+                arr = np.ascontiguousarray(arr, dtype=np.float64).ravel()
+                t[name] = n_real
+                reals.append(arr)
+                n_real += arr.size
+            wsb = lib().md_workspace_bytes(MD_FN_NEWTON, m, sysm.N, sysm.n, d, sysm.M, sysm.max_deg)
+            if wsb == 0:
+                raise MdError(f"path {p}: unsupported sizes")
+            t["ws"] = n_ws
+            n_ws += (wsb + 255) // 256 * 32
+            cost[p] = OC.newton_step(sysm, d, m).table_ops(m)
+            self.meta.append((m, sysm.N, sysm.n, d))
+        dev = torch.device(device)
+        self.npaths = len(paths)
+        self.table = table
+        self.cost = cost
+        self.max_m = int(table["m"].max()) if len(paths) else 1
+        self.max_d = int(table["d"].max()) if len(paths) else 0
+        self.max_deg = int(table["max_deg"].max()) if len(paths) else 0
+        self.paths_dev = torch.as_tensor(table.view(np.uint8).copy(), device=dev)
+        self.ints = torch.as_tensor(np.concatenate(ints) if ints else np.zeros(1, np.int32), device=dev)
+        self.reals = torch.as_tensor(np.concatenate(reals) if reals else np.zeros(1), device=dev)
+        ws = torch.empty(n_ws + 32, dtype=torch.float64, device=dev)
+        off = ((-ws.data_ptr()) % 256) // 8
+        self.ws = ws[off:off + max(n_ws, 1)]
+        if order is None:
+            order = np.argsort(-cost, kind="stable")
+        self.order = torch.as_tensor(np.asarray(order, dtype=np.int32), device=dev)
+        self.counter = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.status = torch.zeros(max(len(paths), 1), dtype=torch.int32, device=dev)
+
+    def x(self, p: int) -> torch.Tensor:
+        m, N, n, d = self.meta[p]
+        o = int(self.table[p]["x"])
+        return self.reals[o:o + 2 * m * (d + 1) * n].view(2, m, d + 1, n)
+
+    def dx_norm(self, p: int) -> torch.Tensor:
+        m = self.meta[p][0]
+        o = int(self.table[p]["dx_norm"])
+        return self.reals[o:o + 2 * m].view(m, 2)
+
+    def reset(self, paths):
+        """Put the start series back (same structure as at construction)."""
+        for p, (_, x) in enumerate(paths):
+            self.x(p).copy_(torch.as_tensor(np.ascontiguousarray(x)))
+        self.status.zero_()
+
+
+def md_batch_lds_bytes(max_m: int, max_d: int, max_deg: int, eval_waves: int) -> int:
+    L = lib()
+    L.md_batch_lds_bytes.argtypes = [ctypes.c_int] * 4
+    L.md_batch_lds_bytes.restype = ctypes.c_size_t
+    return int(L.md_batch_lds_bytes(max_m, max_d, max_deg, eval_waves))
+
+
+def md_newton_batch(batch: BatchedPaths, iters: int, grid: int | None = None,
+                    eval_waves: int | None = None, stream=None):
+    """`iters` Newton steps on every path of the batch in one persistent
+    launch (the library resets the job counter on the stream first)."""
+    L = lib()
+    P, i32 = ctypes.c_void_p, ctypes.c_int
+    L.md_newton_batch.argtypes = [i32, P, P, P, P, P, i32, P, P, i32, i32, i32, i32, i32, P]
+    L.md_newton_batch.restype = ctypes.c_int
+    if eval_waves is None:
+        eval_waves = 4
+        while eval_waves > 1 and md_batch_lds_bytes(batch.max_m, batch.max_d, batch.max_deg,
+                                                     eval_waves) > 64 * 1024:
+            eval_waves -= 1
+    if grid is None:
+        props = torch.cuda.get_device_properties(batch.reals.device)
+        grid = 2 * props.multi_processor_count
+    _check(L.md_newton_batch(batch.npaths, _ptr(batch.paths_dev, torch.uint8), _ptr(batch.order, torch.int32),
+                             _ptr(batch.ints, torch.int32), _ptr(batch.reals), _ptr(batch.ws),
+                             iters, _ptr(batch.counter, torch.int32), _ptr(batch.status, torch.int32),
+                             batch.max_m, batch.max_d, batch.max_deg, grid, eval_waves,
+                             _stream(stream)), "md_newton_batch")
+    return batch

@@ -10,8 +10,10 @@ from __future__ import annotations
 import concurrent.futures as cf
 import glob
 import os
+import re
 import subprocess
 import sys
+import time
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -28,12 +30,36 @@ FLAGS = [
 ]
 
 
+def check_device_asm(asm_path: str) -> list[str]:
+    """Device functions that are real calls (not kernels) and whose long
+    jumps go through s[30:31], the return-address registers: such a function
+    returns to the last jump site instead of its caller, so it must be
+    inlined.  Returns the offending symbols."""
+    text = open(asm_path).read()
+    kernels = set(re.findall(r"\.name:\s+(\S+)", text))
+    labels = [(mm.start(), mm.group(1)) for mm in re.finditer(r"^(_Z\w+):", text, re.M)]
+    bad = []
+    for i, (pos, name) in enumerate(labels):
+        end = labels[i + 1][0] if i + 1 < len(labels) else len(text)
+        if name not in kernels and "s_getpc_b64 s[30:31]" in text[pos:end]:
+            bad.append(name)
+    return bad
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.basename(src)[:-4] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
-    r = subprocess.run(cmd, capture_output=True, text=True)
+    cmd = [HIPCC, *FLAGS, "-save-temps=obj", "-c", src, "-o", obj]
+    t0 = time.time()
+    r = subprocess.run(cmd, capture_output=True, text=True, cwd=OBJ)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
+    if os.environ.get("MDSERIES_BUILD_VERBOSE"):
+        print(f"  {os.path.basename(src)}: {time.time() - t0:.0f} s", flush=True)
+    asm = os.path.join(OBJ, os.path.basename(src)[:-4] + f"-hip-amdgcn-amd-amdhsa-{ARCH}.s")
+    bad = check_device_asm(asm)
+    if bad:
+        raise RuntimeError(f"{src}: device functions would return through a clobbered "
+                           f"return address (force-inline them): {bad}")
     return obj
 
 

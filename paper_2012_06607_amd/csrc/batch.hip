@@ -1,0 +1,214 @@
+// Many independent solution paths in one persistent launch.
+//
+// The paper's job queue (Section 5, Figure 1): all data is set up before
+// the workers start, each job reads shared inputs and writes its own
+// workspace, and a counter guarded by a lock hands out the next job.  Here
+// the workers are workgroups resident on the GPU, the counter is one device
+// atomic, and a job is a whole path: `iters` Newton steps (evaluation and
+// differentiation, QR of A_0, R^{-1} Q^H, the staggered solve, the update)
+// run by that workgroup with barriers between the stages (the paper's stage
+// synchronisation by terminating tasks).  Paths are taken in the order the
+// caller gives (longest first balances the load), and each workgroup
+// dispatches on its path's precision.  Every stage runs the same
+// segment-level code as the single-path entry points, so a batched path
+// gives the same bits as md_newton_step on that path.
+#include "internal.hpp"
+#include "wg.hpp"
+
+namespace mds {
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// max over the workgroup of an exact selection (values are compared, the
+// bits of the largest are kept), through LDS
+template <int M>
+__device__ mdr<M> wg_max(mdr<M> v, mdr<M> *sh) {
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    const mdr<M> t = shfl_down_r<M>(v, o);
+    if (lane_id() < o && md_less<M>(v, t)) v = t;
+  }
+  const int wave = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+  if (lane_id() == 0) sh[wave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int w = 1; w < nw; ++w)
+      if (md_less<M>(v, sh[w])) v = sh[w];
+  __syncthreads();
+  return v;
+}
+
+template <int M>
+__device__ void newton_path(const md_path &p, int iters, const int32_t *__restrict__ ints,
+                            double *__restrict__ reals, double *__restrict__ wsb,
+                            int32_t *__restrict__ status, int path, double *lds_raw,
+                            int eval_waves) {
+  __shared__ QrShared<M> qsh;
+  __shared__ mdr<M> msh[16];
+  const int N = p.N, n = p.n, d = p.d, L = d + 1;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int wave = tid / WAVE, nwaves = nt / WAVE;
+  const NewtonLayout lay(M, N, n, d, p.M, p.max_deg);
+  char *w = reinterpret_cast<char *>(wsb + p.ws);
+  double *f = reinterpret_cast<double *>(w + lay.off_f);
+  double *A = reinterpret_cast<double *>(w + lay.off_A);
+  double *QR = reinterpret_cast<double *>(w + lay.off_QR);
+  double *vd = reinterpret_cast<double *>(w + lay.off_vd);
+  double *beta = reinterpret_cast<double *>(w + lay.off_beta);
+  double *dx = reinterpret_cast<double *>(w + lay.off_dx);
+  const SolveLayout sl(M, N, n, d);
+  double *r = reinterpret_cast<double *>(w + lay.off_solve + sl.off_r);
+  double *W = reinterpret_cast<double *>(w + lay.off_solve + sl.off_G);
+  double *invd = W + size_t(2) * M * n * N;
+  double *x = reals + p.x;
+  EvalArgs a;
+  a.d = d;
+  a.N = N;
+  a.n = n;
+  a.Mt = p.M;
+  a.dc = p.dc;
+  a.Dmax = p.max_deg;
+  a.lay = EvalLayout(M, N, n, d, p.M, p.max_deg);
+  a.S = a.lay.S;
+  a.eq_ptr = ints + p.eq_ptr;
+  a.term_ptr = ints + p.term_ptr;
+  a.factors = ints + p.factors;
+  a.coef = reals + p.coef;
+  a.x = x;
+  a.ws = reinterpret_cast<double *>(w + lay.off_eval);
+  a.Ews = a.lay.E;
+  a.f = f;
+  a.A = A;
+  const int seg = N >= WAVE ? WAVE : pow2_at_least(N);
+  const int seg_up = n >= WAVE ? WAVE : pow2_at_least(n);
+  const int spw = WAVE / seg, nslots = nwaves * spw;
+  const int slot = wave * spw + lane_id() / seg;
+  const int spw_u = WAVE / seg_up, nslots_u = nwaves * spw_u;
+  const int slot_u = wave * spw_u + lane_id() / seg_up;
+  const int rgrp = eval_group(d);
+  const int per_wave = term_lds_series(p.max_deg) * L;
+  mdc<M> *lds = reinterpret_cast<mdc<M> *>(lds_raw);
+  const long Ex = long(L) * n, Er = long(L) * N;
+  int st = 0;
+  for (int it = 0; it < iters; ++it) {
+    // evaluation and differentiation: waves over terms, then the sums
+    if (wave < eval_waves)
+      for (int tau = wave; tau < p.M; tau += eval_waves)
+        eval_term_wave<M>(a, tau, rgrp, lds + wave * per_wave, [] { wave_sync(); });
+    __syncthreads();
+    for (long g = tid; g < long(L) * N * (n + 1); g += nt) eval_accumulate_elem<M>(a, g);
+    __syncthreads();
+    for (long e = tid; e < Er; e += nt) cstore<M>(r, Er, e, c_neg<M>(cload<M>(f, Er, e)));
+    // QR of A_0 (the k = 0 block of A), then W = R^{-1} (Q^H)_{0:n}
+    qr_wg<M, 1>(qsh, N, n, seg, A, long(L) * N * n, QR, vd, beta, st);
+    inv_diag_range<M>(tid, nt, N, n, QR, invd, st);
+    __syncthreads();
+    for (int base = 0; base < N; base += nslots) {
+      const int c = base + slot;
+      pinv_column<M, 1>(c < N, c, N, n, seg, QR, vd, beta, invd, W);
+    }
+    __syncthreads();
+    // staggered substitution
+    for (int k = 0; k <= d; ++k) {
+      for (int base = 0; base < n; base += nslots) {
+        const int i = base + slot;
+        stage_dx_row<M>(i < n, i, k, N, n, d, seg, W, r, dx, st);
+      }
+      __syncthreads();
+      if (k < d) {
+        const long rows = long(d - k) * N;
+        for (long base = 0; base < rows; base += nslots_u) {
+          const long row = base + slot_u;
+          stage_update_row<M>(row < rows, row, k, N, n, d, seg_up, A, dx, r);
+        }
+        __syncthreads();
+      }
+    }
+    // x += dx and the size of the update
+    mdr<M> bd = md_zero<M>(), ba = md_zero<M>();
+    for (long e = tid; e < Ex; e += nt) {
+      const mdc<M> u = cload<M>(dx, Ex, e);
+      cstore<M>(x, Ex, e, c_add<M>(cload<M>(x, Ex, e), u));
+      const mdr<M> a2 = c_abs2<M>(u);
+      if (md_less<M>(ba, a2)) ba = a2;
+      if (e >= long(d) * n && md_less<M>(bd, a2)) bd = a2;
+    }
+    bd = wg_max<M>(bd, msh);
+    ba = wg_max<M>(ba, msh);
+    if (tid == 0 && it == iters - 1) {
+      rstore<M>(reals + p.dx_norm, 2, 0, md_sqrt<M>(bd));
+      rstore<M>(reals + p.dx_norm, 2, 1, md_sqrt<M>(ba));
+    }
+    __syncthreads();
+  }
+  if (st) atomicOr(status + path, st);
+}
+
+__global__ void k_reset_counter(int32_t *counter) { atomicExch(counter, 0); }
+
+__global__ void __launch_bounds__(256) k_newton_batch(int npaths, const md_path *__restrict__ paths,
+                                                      const int32_t *__restrict__ order,
+                                                      const int32_t *__restrict__ ints,
+                                                      double *__restrict__ reals,
+                                                      double *__restrict__ wsb, int iters,
+                                                      int32_t *counter, int32_t *status,
+                                                      int eval_waves) {
+  extern __shared__ double lds_raw[];
+  __shared__ int sh_job;
+  while (true) {
+    if (threadIdx.x == 0) sh_job = atomicAdd(counter, 1);
+    __syncthreads();
+    const int job = sh_job;
+    __syncthreads();
+    if (job >= npaths) break;
+    const int path = order[job];
+    const md_path p = paths[path];
+    const bool ok = p.N >= p.n && p.n >= 1 && p.N <= WAVE && p.d >= 0 && p.max_deg >= 0;
+    if (!ok) {
+      if (threadIdx.x == 0) atomicOr(status + path, MD_ST_BADPATH);
+      continue;
+    }
+    switch (p.m) {
+      case 1: newton_path<1>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves); break;
+      case 2: newton_path<2>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves); break;
+      case 3: newton_path<3>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves); break;
+      case 4: newton_path<4>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves); break;
+      default:
+        if (threadIdx.x == 0) atomicOr(status + path, MD_ST_BADPATH);
+        break;
+    }
+  }
+}
+
+}  // namespace mds
+
+using namespace mds;
+
+extern "C" size_t md_batch_lds_bytes(int max_m, int max_d, int max_deg, int eval_waves) {
+  if (max_m < 1 || max_m > 4 || max_d < 0 || max_deg < 0 || eval_waves < 1) return 0;
+  return sizeof(double) * 2 * size_t(max_m) * size_t(term_lds_series(max_deg)) * (max_d + 1) *
+         eval_waves;
+}
+
+extern "C" int md_newton_batch(int npaths, const md_path *paths, const int32_t *order,
+                               const int32_t *ints, double *reals, double *ws, int iters,
+                               int32_t *counter, int32_t *status, int max_m, int max_d,
+                               int max_deg, int grid, int eval_waves, void *stream) {
+  if (npaths < 0 || iters < 0 || grid < 1 || eval_waves < 1 || eval_waves > 4)
+    return fail(MD_EINVAL, "md_newton_batch: npaths=%d iters=%d grid=%d eval_waves=%d", npaths,
+                iters, grid, eval_waves);
+  if (npaths == 0) return MD_OK;
+  if (!paths || !order || !ints || !reals || !ws || !counter || !status)
+    return fail(MD_ENULL, "md_newton_batch: null pointer");
+  const size_t lds = md_batch_lds_bytes(max_m, max_d, max_deg, eval_waves);
+  if (lds == 0) return fail(MD_EINVAL, "md_newton_batch: max_m=%d must be in 1..4", max_m);
+  if (lds > 64 * 1024)
+    return fail(MD_ESHAPE, "md_newton_batch: %zu bytes of LDS for the evaluation exceed 64 KiB", lds);
+  k_reset_counter<<<dim3(1), dim3(1), 0, (hipStream_t)stream>>>(counter);
+  k_newton_batch<<<dim3(grid), dim3(256), lds, (hipStream_t)stream>>>(
+      npaths, paths, order, ints, reals, ws, iters, counter, status, eval_waves);
+  return check_launch("md_newton_batch");
+}

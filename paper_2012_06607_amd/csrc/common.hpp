@@ -98,7 +98,7 @@ __device__ __forceinline__ mdr<M> seg_reduce_r(mdr<M> s, int seg) {
   return s;
 }
 
-inline int pow2_at_least(int v) {
+__host__ __device__ inline int pow2_at_least(int v) {
   int p = 1;
   while (p < v) p <<= 1;
   return p;

@@ -10,20 +10,10 @@
 // Kernel 2 (one thread per output coefficient): f_i and A_{i,l} are summed
 // over the terms of equation i in term order, from zero.
 #include "internal.hpp"
-#include "layout.hpp"
-#include "series.hpp"
+#include "wg.hpp"
 
 namespace mds {
 
-struct EvalArgs {
-  int d, N, n, Mt, dc, Dmax, S;
-  const int *eq_ptr, *term_ptr, *factors;
-  const double *coef, *x;
-  double *ws;
-  long Ews;
-  double *f, *A;
-  EvalLayout lay;
-};
 
 template <int M>
 __global__ void __launch_bounds__(256) k_eval_terms(EvalArgs a) {
@@ -120,159 +110,21 @@ __global__ void __launch_bounds__(256) k_eval_terms(EvalArgs a) {
   }
 }
 
-// One 64-lane workgroup per term; the term's factor series, its coefficient
-// series and every forward, backward and cross product live in LDS.  The
-// ceil((d+1)/2) coefficient pairs (k, d-k) are spread over groups of r
-// lanes (r a power of two); lane `sub` of a group adds the products with
-// i = sub mod r in increasing i, and the group's partial sums are combined
-// by a fixed-order tree, so the bits do not depend on timing.
-struct TermLds {
-  int Dmax, L;
-  __device__ int xs(int q) const { return q; }                 // factor q = 0..D-1
-  __device__ int cs() const { return Dmax; }
-  __device__ int P(int j) const { return Dmax + 1 + (j - 2); }  // j = 2..D
-  __device__ int Q(int j) const { return 2 * Dmax + (j - 2); }  // j = 2..D-1
-  __device__ int C(int j) const { return 3 * Dmax - 2 + (j - 2); }  // j = 2..D-1
-};
-
-__host__ __device__ inline int term_lds_series(int Dmax) {
-  return Dmax < 2 ? Dmax + 1 : 4 * Dmax - 4;
-}
-
-template <int M>
-__device__ __forceinline__ mdc<M> conv_part(const mdc<M> *X, int dx, const mdc<M> *Y, int k,
-                                            int sub, int r) {
-  const int top = k < dx ? k : dx;
-  mdc<M> acc = c_zero<M>();
-  bool first = true;
-  for (int i = sub; i <= top; i += r) {
-    const mdc<M> t = c_mul<M>(X[i], Y[k - i]);
-    acc = first ? t : c_add<M>(acc, t);
-    first = false;
-  }
-  return acc;
-}
-
-// products z = X Y (deg X <= dx) for the coefficient pairs of this lane's
-// group, written to Z (LDS or, with zs != nullptr, to the workspace slot)
-template <int M>
-__device__ __forceinline__ void conv_group(const mdc<M> *X, int dx, const mdc<M> *Y, mdc<M> *Z,
-                                           int d, int pg, int npg, int sub, int r,
-                                           double *ws, long Ews, long wbase, int mult) {
-  for (int p = pg; p < (d + 2) / 2; p += npg) {
-    const int k1 = p, k2 = d - p;
-    mdc<M> z1 = conv_part<M>(X, dx, Y, k1, sub, r);
-    mdc<M> z2 = conv_part<M>(X, dx, Y, k2, sub, r);
-    z1 = seg_reduce_c<M>(z1, r);
-    z2 = seg_reduce_c<M>(z2, r);
-    if (sub == 0) {
-      if (mult > 1) {
-        z1.re = md_muld<M>(z1.re, double(mult));
-        z1.im = md_muld<M>(z1.im, double(mult));
-        z2.re = md_muld<M>(z2.re, double(mult));
-        z2.im = md_muld<M>(z2.im, double(mult));
-      }
-      if (Z) {
-        Z[k1] = z1;
-        Z[k2] = z2;
-      } else {
-        cstore<M>(ws, Ews, wbase + k1, z1);
-        if (k2 != k1) cstore<M>(ws, Ews, wbase + k2, z2);
-      }
-    }
-  }
-}
-
+// One 64-lane workgroup per term (eval_term_wave): the term's series live
+// in LDS, each coefficient pair's products are split over a group of lanes.
 template <int M>
 __global__ void __launch_bounds__(64) k_eval_terms_wave(EvalArgs a, int r) {
   extern __shared__ double lds_raw[];
-  mdc<M> *lds = reinterpret_cast<mdc<M> *>(lds_raw);
-  const int tau = blockIdx.x;
-  const int d = a.d, L = d + 1;
-  const TermLds T{a.Dmax, L};
-  const int lane = threadIdx.x;
-  const int sub = lane & (r - 1);
-  const int pg = lane / r;
-  const int npg = WAVE / r;
-  const int D = a.term_ptr[tau + 1] - a.term_ptr[tau];
-  if (D > a.Dmax) return;  // the host validates max_deg; never read past the slots
-  const int *v = a.factors + a.term_ptr[tau];
-  auto S = [&](int slot) { return lds + slot * L; };
-  const long Ex = long(L) * a.n;
-  // stage the factor series and the coefficient series
-  for (int e = lane; e < D * L; e += WAVE) {
-    const int q = e / L, k = e - q * L;
-    S(T.xs(q))[k] = cload<M>(a.x, Ex, long(k) * a.n + v[q]);
-  }
-  for (int k = lane; k < L; k += WAVE)
-    S(T.cs())[k] = (k <= a.dc) ? cload<M>(a.coef, long(a.Mt) * (a.dc + 1), long(tau) * (a.dc + 1) + k)
-                               : c_zero<M>();
-  __syncthreads();
-  const int dcu = a.dc < d ? a.dc : d;
-  const long wb = long(tau) * a.S * L;
-  if (D == 0) {
-    for (int k = lane; k < L; k += WAVE) cstore<M>(a.ws, a.Ews, wb + a.lay.val() * L + k, S(T.cs())[k]);
-    return;
-  }
-  if (D == 1) {
-    conv_group<M>(S(T.cs()), dcu, S(T.xs(0)), nullptr, d, pg, npg, sub, r, a.ws, a.Ews,
-                  wb + a.lay.val() * L, 1);
-    for (int k = lane; k < L; k += WAVE) cstore<M>(a.ws, a.Ews, wb + a.lay.der(1) * L + k, S(T.cs())[k]);
-    return;
-  }
-  auto Pj = [&](int j) { return j == 1 ? S(T.xs(0)) : S(T.P(j)); };
-  auto Qj = [&](int j) { return j == D ? S(T.xs(D - 1)) : S(T.Q(j)); };
-  for (int st = 1; st <= D - 1; ++st) {
-    conv_group<M>(Pj(st), d, S(T.xs(st)), S(T.P(st + 1)), d, pg, npg, sub, r, nullptr, 0, 0, 1);
-    const int j = D - st;
-    if (j >= 2) conv_group<M>(S(T.xs(j - 1)), d, Qj(j + 1), S(T.Q(j)), d, pg, npg, sub, r, nullptr, 0, 0, 1);
-    __syncthreads();
-  }
-  for (int j = 2; j <= D - 1; ++j)
-    if (v[j - 1] != v[j - 2]) conv_group<M>(Pj(j - 1), d, Qj(j + 1), S(T.C(j)), d, pg, npg, sub, r, nullptr, 0, 0, 1);
-  __syncthreads();
-  conv_group<M>(S(T.cs()), dcu, Pj(D), nullptr, d, pg, npg, sub, r, a.ws, a.Ews, wb + a.lay.val() * L, 1);
-  for (int j = 1; j <= D; ++j) {
-    if (j > 1 && v[j - 1] == v[j - 2]) continue;
-    int mult = 0;
-    for (int q = 0; q < D; ++q) mult += (v[q] == v[j - 1]);
-    const mdc<M> *cross = (j == 1) ? Qj(2) : (j == D ? Pj(D - 1) : S(T.C(j)));
-    conv_group<M>(S(T.cs()), dcu, cross, nullptr, d, pg, npg, sub, r, a.ws, a.Ews,
-                  wb + a.lay.der(j) * L, mult);
-  }
+  eval_term_wave<M>(a, blockIdx.x, r, reinterpret_cast<mdc<M> *>(lds_raw),
+                    [] { __syncthreads(); });
 }
 
 template <int M>
 __global__ void __launch_bounds__(256) k_eval_accumulate(EvalArgs a) {
-  const int L = a.d + 1;
-  const long per_k = long(a.N) * (a.n + 1);
-  const long total = per_k * L;
+  const long total = long(a.N) * (a.n + 1) * (a.d + 1);
   for (long g = blockIdx.x * long(blockDim.x) + threadIdx.x; g < total;
-       g += long(gridDim.x) * blockDim.x) {
-    const int k = int(g / per_k);
-    const long r = g - k * per_k;
-    const int i = int(r / (a.n + 1));
-    const int l = int(r - long(i) * (a.n + 1));
-    mdc<M> acc = c_zero<M>();
-    for (int tau = a.eq_ptr[i]; tau < a.eq_ptr[i + 1]; ++tau) {
-      int slot = -1;
-      if (l == a.n) {
-        slot = a.lay.val();
-      } else {
-        const int b = a.term_ptr[tau], e = a.term_ptr[tau + 1];
-        if (e - b <= a.Dmax)
-          for (int q = b; q < e; ++q)
-            if (a.factors[q] == l) {
-              slot = a.lay.der(q - b + 1);
-              break;
-            }
-      }
-      if (slot >= 0)
-        acc = c_add<M>(acc, cload<M>(a.ws, a.Ews, (long(tau) * a.S + slot) * L + k));
-    }
-    if (l == a.n) cstore<M>(a.f, long(L) * a.N, long(k) * a.N + i, acc);
-    else cstore<M>(a.A, long(L) * a.N * a.n, (long(k) * a.N + i) * a.n + l, acc);
-  }
+       g += long(gridDim.x) * blockDim.x)
+    eval_accumulate_elem<M>(a, g);
 }
 
 int eval_diff_enqueue(int m, int d, const md_system &sys, const double *x, double *f, double *A,
@@ -298,9 +150,7 @@ int eval_diff_enqueue(int m, int d, const md_system &sys, const double *x, doubl
     if (sys.M > 0) {
       const size_t lds = sizeof(double) * 2 * Mm * size_t(term_lds_series(sys.max_deg)) * (d + 1);
       if (lds <= 64 * 1024) {
-        int r = 1;
-        while (P * r * 2 <= WAVE) r *= 2;
-        k_eval_terms_wave<Mm><<<dim3(sys.M), dim3(64), lds, s>>>(a, r);
+        k_eval_terms_wave<Mm><<<dim3(sys.M), dim3(64), lds, s>>>(a, eval_group(d));
       } else {
         const int T = 256 / P;
         const int blocks = (sys.M + T - 1) / T;

@@ -7,17 +7,18 @@
 
 namespace mds {
 
-inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+__host__ __device__ inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Evaluation: one block of series slots per term.  Slot 0 holds the value
 // c(t) P_D(t); slots 1..Dmax the derivative at factor position j (first
 // occurrences only); then the forward products P_2..P_Dmax, the backward
 // products Q_2..Q_{Dmax-1} and the cross products C_2..C_{Dmax-1}.
 struct EvalLayout {
-  int Dmax, S;
-  long E;  // complex elements in the slot planes
-  size_t bytes;
-  EvalLayout(int m, int N, int n, int d, int M, int max_deg) {
+  int Dmax = 0, S = 0;
+  long E = 0;  // complex elements in the slot planes
+  size_t bytes = 0;
+  EvalLayout() = default;
+  __host__ __device__ EvalLayout(int m, int N, int n, int d, int M, int max_deg) {
     (void)N;
     (void)n;
     Dmax = max_deg;
@@ -36,7 +37,7 @@ struct EvalLayout {
 // W = R^{-1} (Q^H)_{0:n}, then 1/R_ii (n).
 struct SolveLayout {
   size_t off_r, off_G, bytes;
-  SolveLayout(int m, int N, int n, int d) {
+  __host__ __device__ SolveLayout(int m, int N, int n, int d) {
     off_r = 0;
     off_G = align256(sizeof(double) * 2 * m * size_t(d + 1) * N);
     bytes = off_G + align256(sizeof(double) * 2 * m * (size_t(n) * N + n));
@@ -46,7 +47,7 @@ struct SolveLayout {
 // Newton step: f, A, QR factors, dx, then the solve and eval workspaces.
 struct NewtonLayout {
   size_t off_f, off_A, off_QR, off_vd, off_beta, off_dx, off_solve, off_eval, bytes;
-  NewtonLayout(int m, int N, int n, int d, int M, int max_deg) {
+  __host__ __device__ NewtonLayout(int m, int N, int n, int d, int M, int max_deg) {
     const size_t L = size_t(d + 1);
     size_t o = 0;
     off_f = o;

@@ -10,7 +10,7 @@
 // r_{k+j} -= A_j dx_k for all j = 1..d-k at once (the paper's "one job per
 // right hand side update", Section 5).
 #include "internal.hpp"
-#include "layout.hpp"
+#include "wg.hpp"
 
 namespace mds {
 
@@ -31,22 +31,13 @@ __global__ void __launch_bounds__(256) k_copy_rhs(long E, const double *__restri
 template <int M>
 __global__ void __launch_bounds__(64) k_inv_diag(int N, int n, const double *__restrict__ QR,
                                                  double *__restrict__ invd, int32_t *status) {
-  const long E = long(N) * n;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const mdc<M> rii = cload<M>(QR, E, long(i) * n + i);
-    if (rii.re.v[0] == 0.0 && rii.im.v[0] == 0.0 && status) atomicOr(status, MD_ST_SINGULAR);
-    mdc<M> one = c_zero<M>();
-    one.re = md_from<M>(1.0);
-    cstore<M>(invd, n, i, c_div<M>(one, rii));
-  }
+  int st = 0;
+  inv_diag_range<M>(blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, N, n, QR,
+                    invd, st);
+  if (st && status) atomicOr(status, st);
 }
 
-// W = R^{-1} (Q^H)_{0:n}, column by column: column c of the identity is held
-// in registers by a segment of `seg` lanes (lane l keeps rows l, l+seg, ...,
-// at most RPL rows), the n reflectors are applied in order
-// (w = v^H g by a fixed-order segment sum, g -= beta w v), then the back
-// substitution R W_c = g_{0:n} runs with the row owner multiplying by
-// 1/R_ii and broadcasting.  W: row-major n x N (plane stride n*N).
+// W = R^{-1} (Q^H)_{0:n}: one segment of lanes per identity column
 template <int M, int RPL>
 __global__ void __launch_bounds__(256) k_pinv_cols(int N, int n, int seg,
                                                    const double *__restrict__ QR,
@@ -54,133 +45,33 @@ __global__ void __launch_bounds__(256) k_pinv_cols(int N, int n, int seg,
                                                    const double *__restrict__ beta,
                                                    const double *__restrict__ invd,
                                                    double *__restrict__ W) {
-  const long E = long(N) * n;
-  const long EW = long(n) * N;
-  const int lane = lane_id();
-  const int lis = lane & (seg - 1);
-  const int segs_per_wave = WAVE / seg;
   const int gwave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
-  const int c = gwave * segs_per_wave + lane / seg;
-  const bool live = c < N;
-  mdc<M> g[RPL];
-#pragma unroll
-  for (int r = 0; r < RPL; ++r) {
-    g[r] = c_zero<M>();
-    if (live && lis + r * seg == c) g[r].re = md_from<M>(1.0);
-  }
-  for (int j = 0; j < n; ++j) {
-    const mdc<M> v0 = cload<M>(vdiag, n, j);
-    const mdr<M> bet = rload<M>(beta, n, j);
-    mdc<M> vi[RPL];
-    mdc<M> w = c_zero<M>();
-    bool first = true;
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-      const int i = lis + r * seg;
-      vi[r] = c_zero<M>();
-      if (i >= j && i < N) {
-        vi[r] = (i == j) ? v0 : cload<M>(QR, E, long(i) * n + j);
-        const mdc<M> t = c_mul<M>(c_conj<M>(vi[r]), g[r]);
-        w = first ? t : c_add<M>(w, t);
-        first = false;
-      }
-    }
-    w = seg_reduce_c<M>(w, seg);
-    w = shfl_c<M>(w, lane & ~(seg - 1));
-    const mdc<M> bw = c_mulr<M>(w, bet);
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-      const int i = lis + r * seg;
-      if (i >= j && i < N) g[r] = c_sub<M>(g[r], c_mul<M>(bw, vi[r]));
-    }
-  }
-  for (int i = n - 1; i >= 0; --i) {
-    const int owner = i & (seg - 1), ro = i / seg;
-    mdc<M> xi = c_zero<M>();
-#pragma unroll
-    for (int r = 0; r < RPL; ++r)
-      if (r == ro && lis == owner) xi = c_mul<M>(g[r], cload<M>(invd, n, i));
-    xi = shfl_c<M>(xi, (lane & ~(seg - 1)) + owner);
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-      const int l = lis + r * seg;
-      if (l == i) g[r] = xi;
-      else if (l < i) g[r] = c_sub<M>(g[r], c_mul<M>(cload<M>(QR, E, long(l) * n + i), xi));
-    }
-  }
-  if (live) {
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-      const int i = lis + r * seg;
-      if (i < n) cstore<M>(W, EW, long(i) * N + c, g[r]);
-    }
-  }
+  const int c = gwave * (WAVE / seg) + lane_id() / seg;
+  pinv_column<M, RPL>(c < N, c, N, n, seg, QR, vdiag, beta, invd, W);
 }
 
-// dx_k = W r_k: one segment of `seg` lanes per output row, lanes over the
-// N columns, fixed-order segment sum.
+// dx_k = W r_k: one segment per output row
 template <int M>
 __global__ void __launch_bounds__(256) k_stage_dx(int k, int N, int n, int d, int seg,
                                                   const double *__restrict__ G,
                                                   const double *__restrict__ r,
                                                   double *__restrict__ dx, int32_t *status) {
-  const long EG = long(n) * N;
-  const long Er = long(d + 1) * N;
-  const long Ex = long(d + 1) * n;
-  const int lane = lane_id();
-  const int rows_per_wave = WAVE / seg;
   const int gwave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
-  const int i = gwave * rows_per_wave + lane / seg;
-  const int lis = lane & (seg - 1);
-  mdc<M> s = c_zero<M>();
-  if (i < n) {
-    bool first = true;
-    for (int c = lis; c < N; c += seg) {
-      const mdc<M> t = c_mul<M>(cload<M>(G, EG, long(i) * N + c), cload<M>(r, Er, long(k) * N + c));
-      s = first ? t : c_add<M>(s, t);
-      first = false;
-    }
-  }
-  s = seg_reduce_c<M>(s, seg);
-  if (i < n && lis == 0) {
-    cstore<M>(dx, Ex, long(k) * n + i, s);
-    if (!c_finite<M>(s) && status) atomicOr(status, MD_ST_NONFINITE);
-  }
+  const int i = gwave * (WAVE / seg) + lane_id() / seg;
+  int st = 0;
+  stage_dx_row<M>(i < n, i, k, N, n, d, seg, G, r, dx, st);
+  if (st && status) atomicOr(status, st);
 }
 
-// r_{k+j}[i] -= sum_l A_j[i][l] dx_k[l] for j = 1..d-k, i < N: one segment
-// of `seg` lanes per (j, i).
+// r_{k+j} -= A_j dx_k for j = 1..d-k: one segment per (j, row)
 template <int M>
 __global__ void __launch_bounds__(256) k_stage_update(int k, int N, int n, int d, int seg,
                                                       const double *__restrict__ A,
                                                       const double *__restrict__ dx,
                                                       double *__restrict__ r) {
-  const long EA = long(d + 1) * N * n;
-  const long Er = long(d + 1) * N;
-  const long Ex = long(d + 1) * n;
-  const int lane = lane_id();
-  const int rows_per_wave = WAVE / seg;
   const int gwave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
-  const long row = long(gwave) * rows_per_wave + lane / seg;  // (j-1)*N + i
-  const long nrows = long(d - k) * N;
-  const int lis = lane & (seg - 1);
-  const int j = int(row / N) + 1;
-  const int i = int(row - long(j - 1) * N);
-  mdc<M> s = c_zero<M>();
-  if (row < nrows) {
-    bool first = true;
-    for (int l = lis; l < n; l += seg) {
-      const mdc<M> t = c_mul<M>(cload<M>(A, EA, (long(j) * N + i) * n + l),
-                                cload<M>(dx, Ex, long(k) * n + l));
-      s = first ? t : c_add<M>(s, t);
-      first = false;
-    }
-  }
-  s = seg_reduce_c<M>(s, seg);
-  if (row < nrows && lis == 0) {
-    const long e = long(k + j) * N + i;
-    cstore<M>(r, Er, e, c_sub<M>(cload<M>(r, Er, e), s));
-  }
+  const long row = long(gwave) * (WAVE / seg) + lane_id() / seg;
+  stage_update_row<M>(row < long(d - k) * N, row, k, N, n, d, seg, A, dx, r);
 }
 
 int solve_enqueue(int m, int N, int n, int d, const double *QR, const double *vdiag,

@@ -1,0 +1,482 @@
+// Workgroup- and segment-level building blocks shared by the single-path
+// kernels and the batched persistent kernel.
+//
+// A "segment" is a power-of-two group of `seg` lanes inside one wave; it owns
+// one column (QR, R^{-1} Q^H) or one dot product (stage products), lanes over
+// rows, and sums in a fixed tree order.  Every loop that contains a segment
+// reduction has the same trip count for all lanes of a wave.
+#pragma once
+
+#include "layout.hpp"
+#include "series.hpp"
+
+namespace mds {
+
+// ---------------------------------------------------------------------------
+// 1/sqrt(a) by Newton steps y += y (1 - a y^2)/2 that double the working
+// precision (2, 4, 8 limbs, then M), from the hardware value.
+
+template <int P, int M>
+__device__ __forceinline__ mdr<P> trunc(const mdr<M> &a) {
+  mdr<P> z;
+#pragma unroll
+  for (int i = 0; i < P; ++i) z.v[i] = i < M ? a.v[i] : 0.0;
+  return z;
+}
+
+template <int P, int M>
+__device__ __forceinline__ mdr<P> rsqrt_step(const mdr<M> &a, const mdr<P> &y) {
+  const mdr<P> ap = trunc<P, M>(a);
+  mdr<P> t = md_mul<P>(y, y);
+  t = md_mul<P>(ap, t);
+  t = md_sub<P>(md_from<P>(1.0), t);
+  t = md_mul<P>(y, t);
+#pragma unroll
+  for (int i = 0; i < P; ++i) t.v[i] = t.v[i] * 0.5;
+  return md_add<P>(y, t);
+}
+
+template <int M>
+__device__ __forceinline__ mdr<M> rsqrt_doubling(const mdr<M> &a) {
+  const double y0 = 1.0 / __builtin_sqrt(a.v[0]);
+  if constexpr (M == 1) {
+    return md_from<1>(y0);
+  } else {
+    mdr<2> y2 = rsqrt_step<2, M>(a, md_from<2>(y0));
+    if constexpr (M == 2) {
+      return rsqrt_step<2, 2>(a, y2);
+    } else if constexpr (M <= 4) {
+      return rsqrt_step<M, M>(a, trunc<M, 2>(y2));
+    } else {
+      mdr<4> y4 = rsqrt_step<4, M>(a, trunc<4, 2>(y2));
+      if constexpr (M <= 8) {
+        return rsqrt_step<M, M>(a, trunc<M, 4>(y4));
+      } else {
+        mdr<8> y8 = rsqrt_step<8, M>(a, trunc<8, 4>(y4));
+        return rsqrt_step<M, M>(a, trunc<M, 8>(y8));
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Householder QR by one workgroup (Section 4).  For column j: sigma (the
+// 2-norm from the diagonal down) and |alpha| from two waves, then
+// phi = alpha/|alpha|, v_j = (phi (|alpha| + sigma), tail), beta = 1/(sigma
+// (sigma + |alpha|)), R_jj = -phi sigma; every trailing column l gets
+// a_l -= beta (v^H a_l) v, one column per segment.
+
+template <int M>
+struct QrShared {
+  mdr<M> s2, ys, a2, ya, beta;
+  mdc<M> v0;
+};
+
+template <int M, int RPL>
+__device__ __forceinline__ void qr_wg(QrShared<M> &sh, int N, int n, int seg, const double *__restrict__ A0,
+                      long A0E, double *__restrict__ QR, double *__restrict__ vdiag,
+                      double *__restrict__ beta, int &st) {
+  const long E = long(N) * n;
+  const int lane = lane_id();
+  const int wave = threadIdx.x / WAVE;
+  const int nwaves = blockDim.x / WAVE;
+  const int lis = lane & (seg - 1);
+  const int spw = WAVE / seg;
+  const int slot = wave * spw + lane / seg;
+  const int nslots = nwaves * spw;
+  for (long e = threadIdx.x; e < E; e += blockDim.x) cstore<M>(QR, E, e, cload<M>(A0, A0E, e));
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (wave == 0) {
+      mdr<M> s = md_zero<M>();
+      bool first = true;
+      if (lane < seg) {
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+          const int i = lis + r * seg;
+          if (i >= j && i < N) {
+            const mdr<M> t = c_abs2<M>(cload<M>(QR, E, long(i) * n + j));
+            s = first ? t : md_add<M>(s, t);
+            first = false;
+          }
+        }
+      }
+      s = seg_reduce_r<M>(s, seg);
+      if (lane == 0) {
+        sh.s2 = s;
+        sh.ys = rsqrt_doubling<M>(s);
+      }
+    }
+    if (wave == (nwaves > 1 ? 1 : 0) && lane == (nwaves > 1 ? 0 : 1)) {
+      const mdr<M> a2 = c_abs2<M>(cload<M>(QR, E, long(j) * n + j));
+      sh.a2 = a2;
+      sh.ya = rsqrt_doubling<M>(a2);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const mdc<M> alpha = cload<M>(QR, E, long(j) * n + j);
+      const mdr<M> s2 = sh.s2, ys = sh.ys, a2 = sh.a2, ya = sh.ya;
+      const mdr<M> sigma = md_mul<M>(s2, ys);
+      mdr<M> aabs = md_mul<M>(a2, ya);
+      mdc<M> phi = c_zero<M>();
+      phi.re = md_from<M>(1.0);
+      if (a2.v[0] != 0.0) phi = c_mulr<M>(alpha, ya);
+      else aabs = md_zero<M>();
+      mdr<M> bet = md_zero<M>();
+      mdc<M> v0 = c_zero<M>(), rjj = c_zero<M>();
+      if (s2.v[0] == 0.0) {
+        st |= MD_ST_SINGULAR;
+      } else {
+        const mdr<M> sp = md_add<M>(aabs, sigma);
+        v0 = c_mulr<M>(phi, sp);
+        bet = md_div<M>(ys, sp);
+        rjj = c_neg<M>(c_mulr<M>(phi, sigma));
+      }
+      if (!c_finite<M>(rjj) || !md_finite<M>(bet)) st |= MD_ST_NONFINITE;
+      sh.v0 = v0;
+      sh.beta = bet;
+      cstore<M>(vdiag, n, j, v0);
+      rstore<M>(beta, n, j, bet);
+      cstore<M>(QR, E, long(j) * n + j, rjj);
+    }
+    __syncthreads();
+    const mdc<M> v0 = sh.v0;
+    const mdr<M> bet = sh.beta;
+    const int ncols = n - j - 1;
+    for (int base = 0; base < ncols; base += nslots) {
+      const int l = j + 1 + base + slot;
+      const bool live = l < n;
+      mdc<M> vi[RPL], al[RPL];
+      mdc<M> w = c_zero<M>();
+      bool first = true;
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int i = lis + r * seg;
+        vi[r] = c_zero<M>();
+        al[r] = c_zero<M>();
+        if (live && i >= j && i < N) {
+          vi[r] = (i == j) ? v0 : cload<M>(QR, E, long(i) * n + j);
+          al[r] = cload<M>(QR, E, long(i) * n + l);
+          const mdc<M> t = c_mul<M>(c_conj<M>(vi[r]), al[r]);
+          w = first ? t : c_add<M>(w, t);
+          first = false;
+        }
+      }
+      w = seg_reduce_c<M>(w, seg);
+      w = shfl_c<M>(w, lane & ~(seg - 1));
+      const mdc<M> bw = c_mulr<M>(w, bet);
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int i = lis + r * seg;
+        if (live && i >= j && i < N)
+          cstore<M>(QR, E, long(i) * n + l, c_sub<M>(al[r], c_mul<M>(bw, vi[r])));
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// 1 / R_ii for i < n, threads [t0, t0 + nt) of the caller
+template <int M>
+__device__ __forceinline__ void inv_diag_range(int t, int nt, int N, int n, const double *__restrict__ QR,
+                               double *__restrict__ invd, int &st) {
+  const long E = long(N) * n;
+  for (int i = t; i < n; i += nt) {
+    const mdc<M> rii = cload<M>(QR, E, long(i) * n + i);
+    if (rii.re.v[0] == 0.0 && rii.im.v[0] == 0.0) st |= MD_ST_SINGULAR;
+    mdc<M> one = c_zero<M>();
+    one.re = md_from<M>(1.0);
+    cstore<M>(invd, n, i, c_div<M>(one, rii));
+  }
+}
+
+// Column c of W = R^{-1} (Q^H)_{0:n} by one segment (lanes own rows
+// lis, lis+seg, ...): identity column, n reflectors in order, then the back
+// substitution with the row owner multiplying by 1/R_ii and broadcasting.
+// W: row-major n x N.  `live` false: the segment only joins the shuffles.
+template <int M, int RPL>
+__device__ __forceinline__ void pinv_column(bool live, int c, int N, int n, int seg,
+                            const double *__restrict__ QR, const double *__restrict__ vdiag,
+                            const double *__restrict__ beta, const double *__restrict__ invd,
+                            double *__restrict__ W) {
+  const long E = long(N) * n;
+  const long EW = long(n) * N;
+  const int lane = lane_id();
+  const int lis = lane & (seg - 1);
+  mdc<M> g[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    g[r] = c_zero<M>();
+    if (live && lis + r * seg == c) g[r].re = md_from<M>(1.0);
+  }
+  for (int j = 0; j < n; ++j) {
+    const mdc<M> v0 = cload<M>(vdiag, n, j);
+    const mdr<M> bet = rload<M>(beta, n, j);
+    mdc<M> vi[RPL];
+    mdc<M> w = c_zero<M>();
+    bool first = true;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int i = lis + r * seg;
+      vi[r] = c_zero<M>();
+      if (live && i >= j && i < N) {
+        vi[r] = (i == j) ? v0 : cload<M>(QR, E, long(i) * n + j);
+        const mdc<M> t = c_mul<M>(c_conj<M>(vi[r]), g[r]);
+        w = first ? t : c_add<M>(w, t);
+        first = false;
+      }
+    }
+    w = seg_reduce_c<M>(w, seg);
+    w = shfl_c<M>(w, lane & ~(seg - 1));
+    const mdc<M> bw = c_mulr<M>(w, bet);
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int i = lis + r * seg;
+      if (live && i >= j && i < N) g[r] = c_sub<M>(g[r], c_mul<M>(bw, vi[r]));
+    }
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    const int owner = i & (seg - 1), ro = i / seg;
+    mdc<M> xi = c_zero<M>();
+#pragma unroll
+    for (int r = 0; r < RPL; ++r)
+      if (live && r == ro && lis == owner) xi = c_mul<M>(g[r], cload<M>(invd, n, i));
+    xi = shfl_c<M>(xi, (lane & ~(seg - 1)) + owner);
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int l = lis + r * seg;
+      if (!live) continue;
+      if (l == i) g[r] = xi;
+      else if (l < i) g[r] = c_sub<M>(g[r], c_mul<M>(cload<M>(QR, E, long(l) * n + i), xi));
+    }
+  }
+  if (live) {
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int i = lis + r * seg;
+      if (i < n) cstore<M>(W, EW, long(i) * N + c, g[r]);
+    }
+  }
+}
+
+// dx_k[i] = sum_c W[i][c] r_k[c] by one segment
+template <int M>
+__device__ __forceinline__ void stage_dx_row(bool live, int i, int k, int N, int n, int d, int seg,
+                             const double *__restrict__ W, const double *__restrict__ r,
+                             double *__restrict__ dx, int &st) {
+  const long EW = long(n) * N, Er = long(d + 1) * N, Ex = long(d + 1) * n;
+  const int lis = lane_id() & (seg - 1);
+  mdc<M> s = c_zero<M>();
+  bool first = true;
+  if (live)
+    for (int c = lis; c < N; c += seg) {
+      const mdc<M> t = c_mul<M>(cload<M>(W, EW, long(i) * N + c), cload<M>(r, Er, long(k) * N + c));
+      s = first ? t : c_add<M>(s, t);
+      first = false;
+    }
+  s = seg_reduce_c<M>(s, seg);
+  if (live && lis == 0) {
+    cstore<M>(dx, Ex, long(k) * n + i, s);
+    if (!c_finite<M>(s)) st |= MD_ST_NONFINITE;
+  }
+}
+
+// r_{k+j}[i] -= sum_l A_j[i][l] dx_k[l] by one segment; row = (j-1)*N + i
+template <int M>
+__device__ __forceinline__ void stage_update_row(bool live, long row, int k, int N, int n, int d, int seg,
+                                 const double *__restrict__ A, const double *__restrict__ dx,
+                                 double *__restrict__ r) {
+  const long EA = long(d + 1) * N * n, Er = long(d + 1) * N, Ex = long(d + 1) * n;
+  const int lis = lane_id() & (seg - 1);
+  const int j = int(row / N) + 1;
+  const int i = int(row - long(j - 1) * N);
+  mdc<M> s = c_zero<M>();
+  bool first = true;
+  if (live)
+    for (int l = lis; l < n; l += seg) {
+      const mdc<M> t = c_mul<M>(cload<M>(A, EA, (long(j) * N + i) * n + l),
+                                cload<M>(dx, Ex, long(k) * n + l));
+      s = first ? t : c_add<M>(s, t);
+      first = false;
+    }
+  s = seg_reduce_c<M>(s, seg);
+  if (live && lis == 0) {
+    const long e = long(k + j) * N + i;
+    cstore<M>(r, Er, e, c_sub<M>(cload<M>(r, Er, e), s));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// evaluation and differentiation
+
+struct EvalArgs {
+  int d, N, n, Mt, dc, Dmax, S;
+  const int *eq_ptr, *term_ptr, *factors;
+  const double *coef, *x;
+  double *ws;
+  long Ews;
+  double *f, *A;
+  EvalLayout lay;
+};
+
+// LDS series of one term: its factor series, its coefficient series, the
+// forward products P_2..P_D, backward Q_2..Q_{D-1}, cross C_2..C_{D-1}
+struct TermLds {
+  int Dmax;
+  __device__ int xs(int q) const { return q; }
+  __device__ int cs() const { return Dmax; }
+  __device__ int P(int j) const { return Dmax + 1 + (j - 2); }
+  __device__ int Q(int j) const { return 2 * Dmax + (j - 2); }
+  __device__ int C(int j) const { return 3 * Dmax - 2 + (j - 2); }
+};
+
+__host__ __device__ inline int term_lds_series(int Dmax) {
+  return Dmax < 2 ? Dmax + 1 : 4 * Dmax - 4;
+}
+
+// lane r-group width for degree d: the largest power of two r with
+// ceil((d+1)/2) * r <= 64
+__host__ __device__ inline int eval_group(int d) {
+  const int P = (d + 2) / 2;
+  int r = 1;
+  while (P * r * 2 <= 64) r *= 2;
+  return r;
+}
+
+template <int M>
+__device__ __forceinline__ mdc<M> conv_part(const mdc<M> *X, int dx, const mdc<M> *Y, int k,
+                                            int sub, int r) {
+  const int top = k < dx ? k : dx;
+  mdc<M> acc = c_zero<M>();
+  bool first = true;
+  for (int i = sub; i <= top; i += r) {
+    const mdc<M> t = c_mul<M>(X[i], Y[k - i]);
+    acc = first ? t : c_add<M>(acc, t);
+    first = false;
+  }
+  return acc;
+}
+
+// z = X Y (deg X <= dx) truncated at d for the coefficient pairs (k, d-k)
+// of this lane's group; the group's partial sums go through a fixed-order
+// tree; results (times `mult`) to LDS Z or to workspace planes.  Called by
+// all 64 lanes of a wave.
+template <int M>
+__device__ __noinline__ void conv_group(const mdc<M> *X, int dx, const mdc<M> *Y, mdc<M> *Z,
+                                           int d, int r, double *ws, long Ews, long wbase,
+                                           int mult) {
+  const int lane = lane_id();
+  const int sub = lane & (r - 1);
+  const int pg = lane / r;
+  const int npg = WAVE / r;
+  const int P = (d + 2) / 2;
+  for (int base = 0; base < P; base += npg) {
+    const int p = base + pg;
+    const bool live = p < P;
+#pragma unroll 1
+    for (int q = 0; q < 2; ++q) {
+      const int k = live ? (q == 0 ? p : d - p) : 0;
+      mdc<M> z = live ? conv_part<M>(X, dx, Y, k, sub, r) : c_zero<M>();
+      z = seg_reduce_c<M>(z, r);
+      if (live && sub == 0 && (q == 0 || k != p)) {
+        if (mult > 1) {
+          z.re = md_muld<M>(z.re, double(mult));
+          z.im = md_muld<M>(z.im, double(mult));
+        }
+        if (Z) Z[k] = z;
+        else cstore<M>(ws, Ews, wbase + k, z);
+      }
+    }
+  }
+}
+
+// One term by one wave with its series in `lds` (term_lds_series(Dmax) x
+// (d+1) complex numbers): forward and backward products one factor per step,
+// cross products at first positions, then c(t) times the value and the
+// derivatives into the term's workspace slots.  The wave's lanes must all
+// call this; `wave_sync` orders LDS between steps.
+template <int M, class Sync>
+__device__ __forceinline__ void eval_term_wave(const EvalArgs &a, int tau, int r, mdc<M> *lds, Sync wave_sync) {
+  const int d = a.d, L = d + 1;
+  const TermLds T{a.Dmax};
+  const int lane = lane_id();
+  const int D = a.term_ptr[tau + 1] - a.term_ptr[tau];
+  if (D > a.Dmax) return;  // the host validates max_deg
+  const int *v = a.factors + a.term_ptr[tau];
+  auto S = [&](int slot) { return lds + slot * L; };
+  const long Ex = long(L) * a.n;
+  for (int e = lane; e < D * L; e += WAVE) {
+    const int q = e / L, k = e - q * L;
+    S(T.xs(q))[k] = cload<M>(a.x, Ex, long(k) * a.n + v[q]);
+  }
+  for (int k = lane; k < L; k += WAVE)
+    S(T.cs())[k] = (k <= a.dc)
+                       ? cload<M>(a.coef, long(a.Mt) * (a.dc + 1), long(tau) * (a.dc + 1) + k)
+                       : c_zero<M>();
+  wave_sync();
+  const int dcu = a.dc < d ? a.dc : d;
+  const long wb = long(tau) * a.S * L;
+  if (D == 0) {
+    for (int k = lane; k < L; k += WAVE)
+      cstore<M>(a.ws, a.Ews, wb + a.lay.val() * L + k, S(T.cs())[k]);
+    return;
+  }
+  if (D == 1) {
+    conv_group<M>(S(T.cs()), dcu, S(T.xs(0)), nullptr, d, r, a.ws, a.Ews, wb + a.lay.val() * L, 1);
+    for (int k = lane; k < L; k += WAVE)
+      cstore<M>(a.ws, a.Ews, wb + a.lay.der(1) * L + k, S(T.cs())[k]);
+    return;
+  }
+  auto Pj = [&](int j) { return j == 1 ? S(T.xs(0)) : S(T.P(j)); };
+  auto Qj = [&](int j) { return j == D ? S(T.xs(D - 1)) : S(T.Q(j)); };
+  for (int st = 1; st <= D - 1; ++st) {
+    conv_group<M>(Pj(st), d, S(T.xs(st)), S(T.P(st + 1)), d, r, nullptr, 0, 0, 1);
+    const int j = D - st;
+    if (j >= 2) conv_group<M>(S(T.xs(j - 1)), d, Qj(j + 1), S(T.Q(j)), d, r, nullptr, 0, 0, 1);
+    wave_sync();
+  }
+  for (int j = 2; j <= D - 1; ++j)
+    if (v[j - 1] != v[j - 2])
+      conv_group<M>(Pj(j - 1), d, Qj(j + 1), S(T.C(j)), d, r, nullptr, 0, 0, 1);
+  wave_sync();
+  conv_group<M>(S(T.cs()), dcu, Pj(D), nullptr, d, r, a.ws, a.Ews, wb + a.lay.val() * L, 1);
+  for (int j = 1; j <= D; ++j) {
+    if (j > 1 && v[j - 1] == v[j - 2]) continue;
+    int mult = 0;
+    for (int q = 0; q < D; ++q) mult += (v[q] == v[j - 1]);
+    const mdc<M> *cross = (j == 1) ? Qj(2) : (j == D ? Pj(D - 1) : S(T.C(j)));
+    conv_group<M>(S(T.cs()), dcu, cross, nullptr, d, r, a.ws, a.Ews, wb + a.lay.der(j) * L, mult);
+  }
+}
+
+// f_i[k] (l == n) or A_{i,l}[k]: the term slots of equation i added in term
+// order, from zero
+template <int M>
+__device__ __forceinline__ void eval_accumulate_elem(const EvalArgs &a, long g) {
+  const int L = a.d + 1;
+  const long per_k = long(a.N) * (a.n + 1);
+  const int k = int(g / per_k);
+  const long rr = g - k * per_k;
+  const int i = int(rr / (a.n + 1));
+  const int l = int(rr - long(i) * (a.n + 1));
+  mdc<M> acc = c_zero<M>();
+  for (int tau = a.eq_ptr[i]; tau < a.eq_ptr[i + 1]; ++tau) {
+    int slot = -1;
+    if (l == a.n) {
+      slot = a.lay.val();
+    } else {
+      const int b = a.term_ptr[tau], e = a.term_ptr[tau + 1];
+      if (e - b <= a.Dmax)
+        for (int q = b; q < e; ++q)
+          if (a.factors[q] == l) {
+            slot = a.lay.der(q - b + 1);
+            break;
+          }
+    }
+    if (slot >= 0) acc = c_add<M>(acc, cload<M>(a.ws, a.Ews, (long(tau) * a.S + slot) * L + k));
+  }
+  if (l == a.n) cstore<M>(a.f, long(L) * a.N, long(k) * a.N + i, acc);
+  else cstore<M>(a.A, long(L) * a.N * a.n, (long(k) * a.N + i) * a.n + l, acc);
+}
+
+}  // namespace mds

@@ -73,3 +73,23 @@ def test_argument_errors_return_codes(lib):
     assert lib.md_elementwise(2, 99, 4, fake, fake, fake, None) == 1              # unknown op
     assert lib.md_norm2(2, 0, fake, fake, None) == 1                              # empty vector
     assert lib.md_newton_step(2, 8, None, fake, None, fake, 1 << 20, None, None) == 3
+
+
+def test_batch_host_checks(lib):
+    P = ctypes.c_void_p
+    i = ctypes.c_int
+    lib.md_newton_batch.argtypes = [i, P, P, P, P, P, i, P, P, i, i, i, i, i, P]
+    lib.md_batch_lds_bytes.argtypes = [i] * 4
+    lib.md_batch_lds_bytes.restype = ctypes.c_size_t
+    fake = P(4096)
+    args = [fake] * 5
+    # penta double paths are not carried by the batched kernel: rejected on the host
+    assert lib.md_newton_batch(4, *args, 1, fake, fake, 5, 8, 3, 16, 4, None) == 1
+    assert lib.md_newton_batch(4, *args, 1, fake, fake, 4, 8, 3, 0, 4, None) == 1     # grid 0
+    assert lib.md_newton_batch(4, *args, 1, fake, fake, 4, 8, 3, 16, 5, None) == 1    # eval waves
+    assert lib.md_newton_batch(4, None, *args[1:], 1, fake, fake, 4, 8, 3, 16, 4, None) == 3
+    assert lib.md_newton_batch(0, *args, 1, fake, fake, 4, 8, 3, 16, 4, None) == 0    # empty batch
+    # evaluation LDS above 64 KiB is refused (deca-size series on 4 waves)
+    assert lib.md_batch_lds_bytes(4, 200, 4, 4) > 64 * 1024
+    assert lib.md_newton_batch(4, *args, 1, fake, fake, 4, 200, 4, 16, 4, None) == 2
+    assert lib.md_batch_lds_bytes(5, 8, 3, 4) == 0
