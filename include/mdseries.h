@@ -147,8 +147,33 @@ int md_series_solve(int m, int N, int n, int d, const double *QR, const double *
 int md_newton_step(int m, int d, const md_system *sys, double *x, double *dx_norm, void *ws,
                    size_t ws_bytes, int32_t *status, void *stream);
 
+/* Gradient of a real loss L with respect to the series coefficients of the
+ * system, through a converged series solution x(t) (the implicit function
+ * of the system of Section 4 at its root).  With T(A) the block lower
+ * triangular Toeplitz Jacobian of the truncated system in the coefficients
+ * of x and G = dL/dRe x + i dL/dIm x, the call solves T(A)^H lambda = G by
+ * backward substitution over the degrees (the stages of Section 4 in
+ * reverse, with the same single QR of A_0: lambda_k = (R^{-1} Q^H_{0:n})^H
+ * times the updated right hand side), then contracts lambda with the
+ * monomial series of every term: grad c_{tau,j} =
+ * -sum_{k>=j} conj(x^a_{k-j}) lambda_{k,i} for term tau = c_tau x^a of
+ * equation i.  The monomial series are either kept from the evaluation
+ * pass (store_monomials != 0, M (d+1) more complex numbers of workspace) or
+ * recomputed per term inside the contraction (store_monomials == 0).
+ * x, grad_x: planes (2, m, d+1, n), device; grad_coef: out, planes
+ * (2, 2, M, dc+1) (real/imaginary, the two leading limbs of the m-limb
+ * result, term, coefficient), device.  The evaluation runs in m limbs; the
+ * gradient is rounded to double double on output.  Workspace:
+ * md_workspace_bytes(MD_FN_ADJOINT_STORE or MD_FN_ADJOINT, m, N, n, d, M,
+ * max_deg).  N <= 256.  MD_ST_SINGULAR / MD_ST_NONFINITE as md_newton_step.
+ * Errors: as md_newton_step; MD_ESHAPE when a term's series exceed 64 KiB
+ * of LDS. */
+int md_newton_adjoint(int m, int d, const md_system *sys, const double *x, const double *grad_x,
+                      int store_monomials, double *grad_coef, void *ws, size_t ws_bytes,
+                      int32_t *status, void *stream);
+
 /* Workspace size in bytes for an entry point (fn one of MD_FN_*). */
-enum { MD_FN_EVAL = 1, MD_FN_SOLVE = 2, MD_FN_NEWTON = 3 };
+enum { MD_FN_EVAL = 1, MD_FN_SOLVE = 2, MD_FN_NEWTON = 3, MD_FN_ADJOINT = 4, MD_FN_ADJOINT_STORE = 5 };
 size_t md_workspace_bytes(int fn, int m, int N, int n, int d, int M, int max_deg);
 
 /* One multiple-double operation per element, the units of Table 1, for

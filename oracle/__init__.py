@@ -63,6 +63,7 @@ def lib() -> ctypes.CDLL:
             L.orc_qr.argtypes = [i32, i32, i32, P, P, P, P, P]
             L.orc_series_solve.argtypes = [i32, i32, i32, i32, P, P, P, P, P, P, P]
             L.orc_newton_step.argtypes = [i32, i32, i32, i32, i32, i32, P, P, P, P, P, P, P]
+            L.orc_newton_adjoint.argtypes = [i32, i32, i32, i32, i32, i32, P, P, P, P, P, P, P, P]
             L.orc_get_counters.argtypes = [P]
             L.orc_reset_counters.argtypes = []
             _lib = L
@@ -197,3 +198,17 @@ def newton(sysm, x: np.ndarray, iters: int):
         norms.append(nrm)
         status |= st
     return x, norms, status
+
+
+def newton_adjoint(sysm, x: np.ndarray, grad_x: np.ndarray):
+    """Coefficient gradient (planes (2, 2, M, dc+1), double double) of a real
+    loss with upstream gradient grad_x (planes like x) through the converged
+    series x; returns (grad, status)."""
+    x, grad_x = _c(x), _c(grad_x)
+    _, m, L, n = x.shape
+    g = np.zeros((2, 2, sysm.M, sysm.dc + 1))
+    st = np.zeros(1, dtype=np.int32)
+    ep, tp, fa, co = _sys_args(sysm)
+    _check(lib().orc_newton_adjoint(m, L - 1, sysm.N, n, sysm.M, sysm.dc, _p(ep), _p(tp), _p(fa),
+                                    _p(co), _p(x), _p(grad_x), _p(g), _p(st)), "newton_adjoint")
+    return g, int(st[0])

@@ -833,3 +833,128 @@ int orc_newton_step(int m, int d, int N, int n, int M, int dc, const int32_t *eq
     free(f); free(A); free(A0); free(QR); free(vd); free(bet); free(dx);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* adjoint of the converged series solution                                   */
+
+/* z <- Q z with Q = H_0 H_1 ... H_{n-1}: apply H_{n-1} first (z has N entries) */
+static void apply_q(int m, int N, int n, const cmd_t *qr, const cmd_t *vd, const md_t *bet,
+                    cmd_t *z)
+{
+    for (int j = n - 1; j >= 0; --j) {
+        cmd_t w = c_mul(m, c_conj(m, vd[j]), z[j]);
+        for (int i = j + 1; i < N; ++i) w = c_add(m, w, c_mul(m, c_conj(m, qr[(size_t)i * n + j]), z[i]));
+        cmd_t bw = c_mulr(m, w, bet[j]);
+        z[j] = c_sub(m, z[j], c_mul(m, bw, vd[j]));
+        for (int i = j + 1; i < N; ++i) z[i] = c_sub(m, z[i], c_mul(m, bw, qr[(size_t)i * n + j]));
+    }
+}
+
+/*
+ * Gradient of a real loss through the converged series solution x(t) of
+ * f(x(t); c) = 0 mod t^{d+1} (Section 4's system, solved by the Newton
+ * steps), with respect to every coefficient of the system.
+ * The Jacobian of the truncated system in the series coefficients of x is
+ * the block lower triangular Toeplitz matrix T(A) of Section 4, so for the
+ * upstream gradient G (G = dL/dRe x + i dL/dIm x, planes (2, m, d+1, n))
+ * the coefficient gradient is -B^H lambda with T(A)^H lambda = G, B the
+ * derivative of the truncated system in the coefficients.  T(A)^H is block
+ * upper triangular: for k = d down to 0,
+ *   A_0^H lambda_k = G_k - sum_{j=1}^{d-k} A_j^H lambda_{k+j},
+ * solved with the QR factors: R^H y = rhs (forward substitution), then
+ * lambda_k = Q (y, 0).  A coefficient c_{tau,j} (degree j of the coefficient
+ * series of term tau in equation i) enters f_i through c_tau(t) x^a(t), so
+ *   grad c_{tau,j} = - sum_{k=j}^{d} conj(m_{tau,k-j}) lambda_{k,i},
+ * m_tau = x^a (1 for a constant term), by forward products.
+ * x: the converged series (2, m, d+1, n); grad_coef: planes (2, 2, M, dc+1),
+ * the gradient's first two limbs (double double).
+ */
+int orc_newton_adjoint(int m, int d, int N, int n, int M, int dc, const int32_t *eq_ptr,
+                       const int32_t *term_ptr, const int32_t *factors, const double *coef,
+                       const double *x, const double *grad_x, double *grad_coef, int32_t *status)
+{
+    if (!valid_m(m) || d < 0 || n < 1 || N < n || dc < 0) return 1;
+    int L = d + 1;
+    size_t fsz = (size_t)2 * m * L * N, Asz = (size_t)2 * m * L * N * n, A0sz = (size_t)2 * m * N * n;
+    double *f = malloc(sizeof(double) * fsz);
+    double *A = malloc(sizeof(double) * Asz);
+    double *A0 = malloc(sizeof(double) * A0sz);
+    double *QR = malloc(sizeof(double) * A0sz);
+    double *vdp = malloc(sizeof(double) * (size_t)2 * m * n);
+    double *betp = malloc(sizeof(double) * (size_t)m * n);
+    cmd_t *qr = malloc(sizeof(cmd_t) * (size_t)N * n);
+    cmd_t *vd = malloc(sizeof(cmd_t) * (size_t)n);
+    md_t *bet = malloc(sizeof(md_t) * (size_t)n);
+    cmd_t *rhs = malloc(sizeof(cmd_t) * (size_t)L * n);
+    cmd_t *lam = malloc(sizeof(cmd_t) * (size_t)L * N);
+    cmd_t *y = malloc(sizeof(cmd_t) * (size_t)N);
+    cmd_t *ser = malloc(sizeof(cmd_t) * (size_t)L * 3);
+    if (!f || !A || !A0 || !QR || !vdp || !betp || !qr || !vd || !bet || !rhs || !lam || !y || !ser)
+        return 3;
+    int rc = orc_eval_diff(m, d, N, n, M, dc, eq_ptr, term_ptr, factors, coef, x, f, A);
+    if (rc) return rc;
+    int64_t AE = (int64_t)L * N * n, E0 = (int64_t)N * n, xE = (int64_t)L * n;
+    for (int p = 0; p < 2 * m; ++p)
+        memcpy(A0 + (size_t)p * E0, A + (size_t)p * AE, sizeof(double) * (size_t)E0);
+    int32_t st = 0;
+    orc_qr(m, N, n, A0, QR, vdp, betp, &st);
+    *status = st;
+    for (int64_t e = 0; e < E0; ++e) qr[e] = cload(m, QR, E0, e);
+    for (int j = 0; j < n; ++j) { vd[j] = cload(m, vdp, n, j); bet[j] = rload(m, betp, n, j); }
+    for (int64_t e = 0; e < xE; ++e) rhs[e] = cload(m, grad_x, xE, e);
+    for (int k = d; k >= 0; --k) {
+        /* R^H y = rhs_k, R^H lower triangular with (R^H)_{il} = conj(R_li) */
+        for (int i = 0; i < n; ++i) {
+            cmd_t s = rhs[(size_t)k * n + i];
+            for (int l = 0; l < i; ++l)
+                s = c_sub(m, s, c_mul(m, c_conj(m, qr[(size_t)l * n + i]), y[l]));
+            y[i] = c_div(m, s, c_conj(m, qr[(size_t)i * n + i]));
+        }
+        for (int i = n; i < N; ++i) y[i] = c_zero();
+        apply_q(m, N, n, qr, vd, bet, y);
+        for (int i = 0; i < N; ++i) lam[(size_t)k * N + i] = y[i];
+        /* rhs_{k-j} -= A_j^H lambda_k, j = 1..k */
+        for (int j = 1; j <= k; ++j)
+            for (int c = 0; c < n; ++c) {
+                int64_t base = (int64_t)j * N * n;
+                cmd_t t = c_mul(m, c_conj(m, cload(m, A, AE, base + c)), lam[(size_t)k * N]);
+                for (int i = 1; i < N; ++i)
+                    t = c_add(m, t, c_mul(m, c_conj(m, cload(m, A, AE, base + (int64_t)i * n + c)),
+                                          lam[(size_t)k * N + i]));
+                rhs[(size_t)(k - j) * n + c] = c_sub(m, rhs[(size_t)(k - j) * n + c], t);
+            }
+    }
+    /* monomial series and the contraction with lambda */
+    int64_t cE = (int64_t)M * (dc + 1), gE = cE;
+    for (int i = 0; i < N; ++i)
+        for (int tau = eq_ptr[i]; tau < eq_ptr[i + 1]; ++tau) {
+            const int32_t *v = factors + term_ptr[tau];
+            int D = term_ptr[tau + 1] - term_ptr[tau];
+            cmd_t *mono = ser, *xv = ser + L, *tmp = ser + 2 * L;
+            for (int k = 0; k < L; ++k) mono[k] = c_zero();
+            mono[0].re = md_from_d(m, 1.0);
+            if (D >= 1)
+                for (int k = 0; k < L; ++k) mono[k] = cload(m, x, xE, (int64_t)k * n + v[0]);
+            for (int q = 1; q < D; ++q) {
+                for (int k = 0; k < L; ++k) xv[k] = cload(m, x, xE, (int64_t)k * n + v[q]);
+                ser_mul_mem(m, d, d, mono, xv, tmp);
+                for (int k = 0; k < L; ++k) mono[k] = tmp[k];
+            }
+            for (int j = 0; j <= dc; ++j) {
+                cmd_t g = c_zero();
+                if (j <= d) {
+                    g = c_mul(m, c_conj(m, mono[0]), lam[(size_t)j * N + i]);
+                    for (int k = j + 1; k <= d; ++k)
+                        g = c_add(m, g, c_mul(m, c_conj(m, mono[k - j]), lam[(size_t)k * N + i]));
+                }
+                g = c_neg(m, g);
+                for (int l = 0; l < 2; ++l) {
+                    grad_coef[(int64_t)l * gE + (int64_t)tau * (dc + 1) + j] = l < m ? g.re.v[l] : 0.0;
+                    grad_coef[(int64_t)(2 + l) * gE + (int64_t)tau * (dc + 1) + j] = l < m ? g.im.v[l] : 0.0;
+                }
+            }
+        }
+    free(f); free(A); free(A0); free(QR); free(vdp); free(betp); free(qr); free(vd); free(bet);
+    free(rhs); free(lam); free(y); free(ser);
+    return 0;
+}

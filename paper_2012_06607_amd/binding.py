@@ -19,7 +19,7 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libmdseries.so")
 
-MD_FN_EVAL, MD_FN_SOLVE, MD_FN_NEWTON = 1, 2, 3
+MD_FN_EVAL, MD_FN_SOLVE, MD_FN_NEWTON, MD_FN_ADJOINT, MD_FN_ADJOINT_STORE = 1, 2, 3, 4, 5
 MD_ST_SINGULAR, MD_ST_NONFINITE = 1, 2
 OPS = {"add": 0, "sub": 1, "mul": 2, "div": 3, "sqrt": 4, "rsqrt": 5, "muld": 6,
        "cadd": 7, "csub": 8, "cmul": 9, "cdiv": 10, "cabs2": 11}
@@ -54,6 +54,8 @@ def lib() -> ctypes.CDLL:
         L.md_qr.argtypes = [i32, i32, i32, P, P, P, P, P, P]
         L.md_series_solve.argtypes = [i32, i32, i32, i32, P, P, P, P, P, P, P, sz, P, P]
         L.md_newton_step.argtypes = [i32, i32, ctypes.POINTER(md_system), P, P, P, sz, P, P]
+        L.md_newton_adjoint.argtypes = [i32, i32, ctypes.POINTER(md_system), P, P, i32, P, P, sz,
+                                        P, P]
         L.md_workspace_bytes.argtypes = [i32, i32, i32, i32, i32, i32, i32]
         L.md_workspace_bytes.restype = sz
         L.md_elementwise.argtypes = [i32, i32, i64, P, P, P, P]
@@ -152,6 +154,20 @@ class DeviceSystem:
                               self.eq_ptr.data_ptr(), self.term_ptr.data_ptr(),
                               self.factors.data_ptr(), self.coef.data_ptr())
 
+    def with_coef(self, coef: torch.Tensor) -> "DeviceSystem":
+        """The same structure with the coefficients read from `coef`
+        (planes (2, m, M, dc+1) on the device; kept alive by the result)."""
+        h = self.host
+        if tuple(coef.shape) != (2, h.m, h.M, h.dc + 1):
+            raise MdError(f"coef must have shape (2, m, M, dc+1), got {tuple(coef.shape)}")
+        _ptr(coef)
+        other = object.__new__(DeviceSystem)
+        other.__dict__.update(self.__dict__)
+        other.coef = coef
+        other.desc = md_system(h.N, h.n, h.M, h.dc, h.max_deg, self.eq_ptr.data_ptr(),
+                               self.term_ptr.data_ptr(), self.factors.data_ptr(), coef.data_ptr())
+        return other
+
     @property
     def N(self):
         return self.host.N
@@ -239,6 +255,33 @@ def md_newton_step(sysd: DeviceSystem, x: torch.Tensor, dx_norm=None, ws=None, s
                                 _ptr(ws, torch.uint8), ws.numel(), _ptr(status, torch.int32),
                                 _stream(stream)), "md_newton_step")
     return x, dx_norm, status
+
+
+def md_newton_adjoint(sysd: DeviceSystem, x: torch.Tensor, grad_x: torch.Tensor,
+                      store_monomials: bool = True, grad_coef=None, ws=None, status=None,
+                      stream=None):
+    """Coefficient gradient of a real loss through the converged series x
+    (2, m, d+1, n) given grad_x = dL/dRe x + i dL/dIm x (same planes);
+    returns (grad_coef planes (2, 2, M, dc+1) in double double, status)."""
+    m = _limbs(x)
+    _, _, L, n = x.shape
+    if tuple(grad_x.shape) != tuple(x.shape):
+        raise MdError(f"md_newton_adjoint: grad_x shape {tuple(grad_x.shape)} != x {tuple(x.shape)}")
+    h = sysd.host
+    if grad_coef is None:
+        grad_coef = torch.empty((2, 2, h.M, h.dc + 1), dtype=torch.float64, device=x.device)
+    elif tuple(grad_coef.shape) != (2, 2, h.M, h.dc + 1):
+        raise MdError(f"md_newton_adjoint: grad_coef shape {tuple(grad_coef.shape)}")
+    if ws is None:
+        fn = MD_FN_ADJOINT_STORE if store_monomials else MD_FN_ADJOINT
+        ws = workspace(fn, m, sysd.N, n, L - 1, h.M, h.max_deg, x.device)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=x.device)
+    _check(lib().md_newton_adjoint(m, L - 1, ctypes.byref(sysd.desc), _ptr(x), _ptr(grad_x),
+                                   int(bool(store_monomials)), _ptr(grad_coef),
+                                   _ptr(ws, torch.uint8), ws.numel(), _ptr(status, torch.int32),
+                                   _stream(stream)), "md_newton_adjoint")
+    return grad_coef, status
 
 
 def md_elementwise(op: str, a: torch.Tensor, b: torch.Tensor | None = None, stream=None):

@@ -40,6 +40,8 @@ extern "C" size_t md_workspace_bytes(int fn, int m, int N, int n, int d, int M, 
     case MD_FN_EVAL: return mds::EvalLayout(m, N, n, d, M, max_deg).bytes;
     case MD_FN_SOLVE: return mds::SolveLayout(m, N, n, d).bytes;
     case MD_FN_NEWTON: return mds::NewtonLayout(m, N, n, d, M, max_deg).bytes;
+    case MD_FN_ADJOINT: return mds::AdjointLayout(m, N, n, d, M, max_deg, false).bytes;
+    case MD_FN_ADJOINT_STORE: return mds::AdjointLayout(m, N, n, d, M, max_deg, true).bytes;
     default: return 0;
   }
 }

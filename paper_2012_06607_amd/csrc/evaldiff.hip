@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(256) k_eval_accumulate(EvalArgs a) {
 }
 
 int eval_diff_enqueue(int m, int d, const md_system &sys, const double *x, double *f, double *A,
-                      void *ws, size_t ws_bytes, hipStream_t s) {
+                      void *ws, size_t ws_bytes, hipStream_t s, double *mono) {
   if (d < 0) return fail(MD_EINVAL, "md_poly_eval_diff: d=%d < 0", d);
   if (sys.N < 1 || sys.n < 1 || sys.M < 0 || sys.dc < 0 || sys.max_deg < 0)
     return fail(MD_ESHAPE, "md_poly_eval_diff: bad system sizes N=%d n=%d M=%d dc=%d max_deg=%d",
@@ -145,6 +145,7 @@ int eval_diff_enqueue(int m, int d, const md_system &sys, const double *x, doubl
                 ws_bytes, lay.bytes);
   EvalArgs a{d, sys.N, sys.n, sys.M, sys.dc, sys.max_deg, lay.S, sys.eq_ptr, sys.term_ptr,
              sys.factors, sys.coef, x, static_cast<double *>(ws), lay.E, f, A, lay};
+  a.mono = mono;
   return dispatch_m(m, [&](auto Mc) {
     constexpr int Mm = decltype(Mc)::value;
     if (sys.M > 0) {
@@ -152,6 +153,8 @@ int eval_diff_enqueue(int m, int d, const md_system &sys, const double *x, doubl
       if (lds <= 64 * 1024) {
         k_eval_terms_wave<Mm><<<dim3(sys.M), dim3(64), lds, s>>>(a, eval_group(d));
       } else {
+        if (mono)
+          return fail(MD_ESHAPE, "stored monomials need the one-wave evaluation (%zu bytes of LDS)", lds);
         const int T = 256 / P;
         const int blocks = (sys.M + T - 1) / T;
         k_eval_terms<Mm><<<dim3(blocks), dim3(256), 0, s>>>(a);

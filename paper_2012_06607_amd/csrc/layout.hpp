@@ -70,4 +70,17 @@ struct NewtonLayout {
   }
 };
 
+// Adjoint: the Newton step's buffers, then lambda (d+1, N) and, when the
+// monomial series are stored, (M, d+1) of them.
+struct AdjointLayout {
+  NewtonLayout nl;
+  size_t off_lam, off_mono, bytes;
+  __host__ __device__ AdjointLayout(int m, int N, int n, int d, int M, int max_deg, bool store)
+      : nl(m, N, n, d, M, max_deg) {
+    off_lam = nl.bytes;
+    off_mono = off_lam + align256(sizeof(double) * 2 * m * size_t(d + 1) * N);
+    bytes = off_mono + (store ? align256(sizeof(double) * 2 * m * size_t(M > 0 ? M : 1) * (d + 1)) : 0);
+  }
+};
+
 }  // namespace mds

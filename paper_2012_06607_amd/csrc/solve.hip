@@ -74,6 +74,27 @@ __global__ void __launch_bounds__(256) k_stage_update(int k, int N, int n, int d
   stage_update_row<M>(row < long(d - k) * N, row, k, N, n, d, seg, A, dx, r);
 }
 
+int pinv_enqueue(int m, int N, int n, const double *QR, const double *vdiag, const double *beta,
+                 double *invd, double *W, int32_t *status, hipStream_t s) {
+  return dispatch_m(m, [&](auto Mc) {
+    constexpr int Mm = decltype(Mc)::value;
+    k_inv_diag<Mm><<<dim3((n + 63) / 64), dim3(64), 0, s>>>(N, n, QR, invd, status);
+    const int seg = N >= WAVE ? WAVE : pow2_at_least(N);
+    const long waves = (long(N) * seg + WAVE - 1) / WAVE;
+    const unsigned blk = unsigned((waves + 3) / 4);
+    const int rpl = (N + seg - 1) / seg;
+    if (rpl == 1)
+      k_pinv_cols<Mm, 1><<<dim3(blk), dim3(256), 0, s>>>(N, n, seg, QR, vdiag, beta, invd, W);
+    else if (rpl == 2)
+      k_pinv_cols<Mm, 2><<<dim3(blk), dim3(256), 0, s>>>(N, n, seg, QR, vdiag, beta, invd, W);
+    else if (rpl <= 4)
+      k_pinv_cols<Mm, 4><<<dim3(blk), dim3(256), 0, s>>>(N, n, seg, QR, vdiag, beta, invd, W);
+    else
+      return fail(MD_ESHAPE, "R^{-1} Q^H: N=%d above 256", N);
+    return check_launch("R^{-1} Q^H");
+  });
+}
+
 int solve_enqueue(int m, int N, int n, int d, const double *QR, const double *vdiag,
                   const double *beta, const double *A, const double *b, bool negate_b,
                   double *dx, void *ws, size_t ws_bytes, int32_t *status, hipStream_t s) {
@@ -95,22 +116,7 @@ int solve_enqueue(int m, int N, int n, int d, const double *QR, const double *vd
     if (blocks > 65536) blocks = 65536;
     k_copy_rhs<Mm><<<dim3(unsigned(blocks)), dim3(256), 0, s>>>(Er, b, negate_b, r);
     double *invd = G + size_t(2) * Mm * n * N;
-    k_inv_diag<Mm><<<dim3((n + 63) / 64), dim3(64), 0, s>>>(N, n, QR, invd, status);
-    {
-      const int seg = N >= WAVE ? WAVE : pow2_at_least(N);
-      const long waves = (long(N) * seg + WAVE - 1) / WAVE;
-      const unsigned blk = unsigned((waves + 3) / 4);
-      const int rpl = (N + seg - 1) / seg;
-      if (rpl == 1)
-        k_pinv_cols<Mm, 1><<<dim3(blk), dim3(256), 0, s>>>(N, n, seg, QR, vdiag, beta, invd, G);
-      else if (rpl == 2)
-        k_pinv_cols<Mm, 2><<<dim3(blk), dim3(256), 0, s>>>(N, n, seg, QR, vdiag, beta, invd, G);
-      else if (rpl <= 4)
-        k_pinv_cols<Mm, 4><<<dim3(blk), dim3(256), 0, s>>>(N, n, seg, QR, vdiag, beta, invd, G);
-      else
-        return fail(MD_ESHAPE, "md_series_solve: N=%d above 256", N);
-    }
-    int rc = check_launch("md_series_solve (setup)");
+    int rc = pinv_enqueue(Mm, N, n, QR, vdiag, beta, invd, G, status, s);
     if (rc) return rc;
     const int seg_dx = N >= WAVE ? WAVE : pow2_at_least(N);
     const int seg_up = n >= WAVE ? WAVE : pow2_at_least(n);

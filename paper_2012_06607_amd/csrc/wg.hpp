@@ -317,6 +317,7 @@ struct EvalArgs {
   long Ews;
   double *f, *A;
   EvalLayout lay;
+  double *mono = nullptr;  // when set: the monomial series x^a of each term, planes (2, m, Mt, d+1)
 };
 
 // LDS series of one term: its factor series, its coefficient series, the
@@ -416,6 +417,14 @@ __device__ __forceinline__ void eval_term_wave(const EvalArgs &a, int tau, int r
   wave_sync();
   const int dcu = a.dc < d ? a.dc : d;
   const long wb = long(tau) * a.S * L;
+  const long Em = long(a.Mt) * L;
+  if (a.mono && D <= 1)
+    for (int k = lane; k < L; k += WAVE) {
+      mdc<M> z = c_zero<M>();
+      if (D == 1) z = S(T.xs(0))[k];
+      else if (k == 0) z.re = md_from<M>(1.0);
+      cstore<M>(a.mono, Em, long(tau) * L + k, z);
+    }
   if (D == 0) {
     for (int k = lane; k < L; k += WAVE)
       cstore<M>(a.ws, a.Ews, wb + a.lay.val() * L + k, S(T.cs())[k]);
@@ -438,6 +447,8 @@ __device__ __forceinline__ void eval_term_wave(const EvalArgs &a, int tau, int r
   for (int j = 2; j <= D - 1; ++j)
     if (v[j - 1] != v[j - 2])
       conv_group<M>(Pj(j - 1), d, Qj(j + 1), S(T.C(j)), d, r, nullptr, 0, 0, 1);
+  if (a.mono)
+    for (int k = lane; k < L; k += WAVE) cstore<M>(a.mono, Em, long(tau) * L + k, Pj(D)[k]);
   wave_sync();
   conv_group<M>(S(T.cs()), dcu, Pj(D), nullptr, d, r, a.ws, a.Ews, wb + a.lay.val() * L, 1);
   for (int j = 1; j <= D; ++j) {
@@ -477,6 +488,74 @@ __device__ __forceinline__ void eval_accumulate_elem(const EvalArgs &a, long g) 
   }
   if (l == a.n) cstore<M>(a.f, long(L) * a.N, long(k) * a.N + i, acc);
   else cstore<M>(a.A, long(L) * a.N * a.n, (long(k) * a.N + i) * a.n + l, acc);
+}
+
+// ---------------------------------------------------------------------------
+// adjoint pieces
+
+// The monomial series x^a of term tau into LDS by forward products (one
+// wave); returns the slot holding it.  Slots: factor series 0..D-1, then the
+// products P_2..P_D.
+template <int M, class Sync>
+__device__ __forceinline__ const mdc<M> *monomial_wave(const EvalArgs &a, int tau, int r,
+                                                       mdc<M> *lds, Sync wave_sync) {
+  const int d = a.d, L = d + 1;
+  const int lane = lane_id();
+  const int D = a.term_ptr[tau + 1] - a.term_ptr[tau];
+  const int *v = a.factors + a.term_ptr[tau];
+  auto S = [&](int slot) { return lds + slot * L; };
+  const long Ex = long(L) * a.n;
+  if (D == 0) {
+    for (int k = lane; k < L; k += WAVE) {
+      mdc<M> z = c_zero<M>();
+      if (k == 0) z.re = md_from<M>(1.0);
+      S(0)[k] = z;
+    }
+    wave_sync();
+    return S(0);
+  }
+  for (int e = lane; e < D * L; e += WAVE) {
+    const int q = e / L, k = e - q * L;
+    S(q)[k] = cload<M>(a.x, Ex, long(k) * a.n + v[q]);
+  }
+  wave_sync();
+  for (int st = 1; st <= D - 1; ++st) {
+    const mdc<M> *prev = st == 1 ? S(0) : S(D + st - 2);
+    conv_group<M>(prev, d, S(st), S(D + st - 1), d, r, nullptr, 0, 0, 1);
+    wave_sync();
+  }
+  return D == 1 ? S(0) : S(2 * D - 2);
+}
+
+// grad c_{tau,j} = -sum_{k=j}^{d} conj(mono_{k-j}) lambda_{k,i}, j = 0..dc,
+// by one wave (lanes over k, fixed-order wave sum); the first two limbs are
+// stored (planes (2, 2, Mt, dc+1)).
+template <int M>
+__device__ __forceinline__ void contract_wave(const mdc<M> *mono, long mstride, const double *mono_g,
+                                              long Em, long mbase, const double *lam, int N, int i,
+                                              int d, int dc, int tau, int Mt, double *grad) {
+  const int lane = lane_id();
+  const long El = long(d + 1) * N;
+  const long Eg = long(Mt) * (dc + 1);
+  for (int j = 0; j <= dc; ++j) {
+    mdc<M> s = c_zero<M>();
+    bool first = true;
+    for (int k = j + lane; k <= d; k += WAVE) {
+      const mdc<M> mk = mono ? mono[(k - j) * mstride] : cload<M>(mono_g, Em, mbase + (k - j));
+      const mdc<M> t = c_mul<M>(c_conj<M>(mk), cload<M>(lam, El, long(k) * N + i));
+      s = first ? t : c_add<M>(s, t);
+      first = false;
+    }
+    s = seg_reduce_c<M>(s, WAVE);
+    if (lane == 0) {
+      const long e = long(tau) * (dc + 1) + j;
+#pragma unroll
+      for (int l = 0; l < 2; ++l) {
+        grad[l * Eg + e] = l < M ? -s.re.v[l] : 0.0;
+        grad[(2 + l) * Eg + e] = l < M ? -s.im.v[l] : 0.0;
+      }
+    }
+  }
 }
 
 }  // namespace mds

@@ -52,6 +52,10 @@ def test_workspace_sizes(lib):
     # workspace grows linearly in the number of terms and quadratically in N
     assert f(1, 2, 8, 8, 8, 160, 3) > f(1, 2, 8, 8, 8, 80, 3)
     assert f(2, 2, 64, 64, 8, 0, 0) > f(2, 2, 32, 32, 8, 0, 0)
+    # adjoint: the Newton workspace plus lambda; storing the monomial series
+    # adds at least M (d+1) complex md numbers
+    assert f(4, 4, 32, 32, 16, 320, 3) > f(3, 4, 32, 32, 16, 320, 3)
+    assert f(5, 4, 32, 32, 16, 320, 3) >= f(4, 4, 32, 32, 16, 320, 3) + 2 * 4 * 8 * 320 * 17
 
 
 def test_argument_errors_return_codes(lib):
@@ -73,6 +77,37 @@ def test_argument_errors_return_codes(lib):
     assert lib.md_elementwise(2, 99, 4, fake, fake, fake, None) == 1              # unknown op
     assert lib.md_norm2(2, 0, fake, fake, None) == 1                              # empty vector
     assert lib.md_newton_step(2, 8, None, fake, None, fake, 1 << 20, None, None) == 3
+    lib.md_newton_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_int, P, P,
+                                      ctypes.c_size_t, P, P]
+    assert lib.md_newton_adjoint(2, 8, None, fake, fake, 1, fake, fake, 1 << 20, None, None) == 3
+
+
+class _System(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("n", ctypes.c_int32), ("M", ctypes.c_int32),
+                ("dc", ctypes.c_int32), ("max_deg", ctypes.c_int32),
+                ("eq_ptr", ctypes.c_void_p), ("term_ptr", ctypes.c_void_p),
+                ("factors", ctypes.c_void_p), ("coef", ctypes.c_void_p)]
+
+
+def test_adjoint_host_checks(lib):
+    P = ctypes.c_void_p
+    lib.md_newton_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(_System), P, P,
+                                      ctypes.c_int, P, P, ctypes.c_size_t, P, P]
+    lib.md_workspace_bytes.restype = ctypes.c_size_t
+    lib.md_workspace_bytes.argtypes = [ctypes.c_int] * 7
+    fake = P(4096)
+    sysd = _System(8, 8, 80, 1, 3, 4096, 4096, 4096, 4096)
+    need = lib.md_workspace_bytes(5, 2, 8, 8, 8, 80, 3)
+    call = lambda m, d, s, ws, nb, store=1: lib.md_newton_adjoint(  # noqa: E731
+        m, d, ctypes.byref(s), fake, fake, store, fake, ws, nb, None, None)
+    assert call(2, -1, sysd, fake, need) == 1                       # negative degree
+    assert call(6, 8, sysd, fake, need) == 1                        # m = 6
+    assert call(2, 8, _System(4, 8, 80, 1, 3, 4096, 4096, 4096, 4096), fake, need) == 2  # N < n
+    assert call(2, 8, _System(300, 8, 80, 1, 3, 4096, 4096, 4096, 4096), fake, need) == 2
+    assert call(2, 8, sysd, P(4096), need - 1) == 4                 # workspace too small
+    assert call(2, 8, sysd, P(4096 + 8), need) == 4                 # misaligned workspace
+    assert lib.md_newton_adjoint(2, 8, ctypes.byref(sysd), None, fake, 1, fake, fake, need,
+                                 None, None) == 3                   # x missing
 
 
 def test_batch_host_checks(lib):
