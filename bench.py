@@ -36,6 +36,35 @@ WORKLOAD = ("qd complex, n=N=32, d=16: eval/diff of a 32x32 system (16 monomials
             "per equation) + Householder QR of A0 (cond 1e3) + staggered block Toeplitz solve")
 
 
+# HBM traffic of one k_qr launch (quad double, 32 x 32) from two rocprofv3
+# --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch,
+# mean over the dispatches), each scaled by what the same counter reads for
+# a plain 256 MiB device copy in the same run (--copy-mib 256: FETCH_SIZE
+# read 131088 KiB for 262144 KiB moved, WRITE_SIZE 262147 KiB).  Valid only
+# for the kernel sources it was taken on: the figure is dropped when their
+# hash differs.
+QR_TRAFFIC = {
+    "fetch_kib": 134.6, "fetch_scale": 262144 / 131088.2,
+    "write_kib": 67.0, "write_scale": 262144 / 262146.8,
+    "sources": ("qr.hip", "internal.hpp", "common.hpp", "md.hpp", "wg.hpp", "layout.hpp",
+                "series.hpp"),
+    "sha256": "bb15957c50d71f61492f439d6df4a31e341a42d7dcb59a18a121cf51a64081f9",
+}
+
+
+def qr_traffic_bytes():
+    """k_qr's measured HBM bytes per launch, or None once its sources changed."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in QR_TRAFFIC["sources"]:
+        with open(os.path.join(ROOT, "paper_2012_06607_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != QR_TRAFFIC["sha256"]:
+        return None
+    t = QR_TRAFFIC
+    return int(round(1024 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])))
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -48,6 +77,12 @@ def parse():
                     help="skip the batched-paths measurement (1024 paths, one persistent launch)")
     ap.add_argument("--batch-paths", type=int, default=1024)
     ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint measurement (32 unknowns, d = 16, quad double)")
+    ap.add_argument("--adj-reps", type=int, default=20)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="before timing, run one plain device copy of this many MiB (a "
+                         "reference of known traffic for hardware byte counters)")
     return ap.parse_args()
 
 
@@ -159,6 +194,65 @@ def batched_measure(args, B, OC):
     }
 
 
+def adjoint_measure(args, B, OC):
+    """Quad double series Newton on a 32-unknown system (8 monomials of degree
+    <= 3, a constant and a t-term per equation: 320 coefficients), d = 16,
+    8 steps from the root at t = 0; then the coefficient gradient of
+    L = sum |x_k|^2 by md_newton_adjoint with the monomial series stored and
+    recomputed, each against the forward Newton step on the same GPU."""
+    import numpy as np
+    import torch
+    from paper_2012_06607_amd import inputs as I
+    m, n, d, iters = 4, 32, 16, 8
+    sysm, x0 = I.newton_system((5, 0), n, m, terms=8, max_deg=3)
+    sd = B.DeviceSystem(sysm)
+    x = torch.as_tensor(I.series_start(x0, d), device="cuda")
+    stream = torch.cuda.current_stream()
+    ws_n = B.workspace(B.MD_FN_NEWTON, m, n, n, d, sysm.M, sysm.max_deg)
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    nrm = torch.empty((m, 2), dtype=torch.float64, device="cuda")
+
+    def timed(fn, reps):
+        out = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            out.append(e0.elapsed_time(e1))
+        return float(np.median(out))
+
+    ms_fwd = timed(lambda: [B.md_newton_step(sd, x, nrm, ws_n, st, stream)
+                            for _ in range(iters)], 1) / iters
+    G = 2 * x
+    res = {}
+    grads = {}
+    for store in (True, False):
+        fn = B.MD_FN_ADJOINT_STORE if store else B.MD_FN_ADJOINT
+        ws = B.workspace(fn, m, n, n, d, sysm.M, sysm.max_deg)
+        g = torch.empty((2, 2, sysm.M, sysm.dc + 1), dtype=torch.float64, device="cuda")
+        B.md_newton_adjoint(sd, x, G, store, g, ws, st, stream)
+        torch.cuda.synchronize()
+        ms = timed(lambda: B.md_newton_adjoint(sd, x, G, store, g, ws, st, stream), args.adj_reps)
+        key = "store" if store else "recompute"
+        res[key] = {"ms": round(ms, 4), "workspace_bytes": int(ws.numel())}
+        grads[key] = g.clone()
+    ops = OC.adjoint(sysm, d, m).table_ops(m)
+    return {
+        "workload": "qd, n=32, d=16, 256 monomials of degree <= 3 + 32 constants + 32 t-terms "
+                    "(320 coefficients), gradient of sum |x_k|^2 in double double",
+        "newton_step_ms": round(ms_fwd, 4),
+        "adjoint": res,
+        "adjoint_over_newton_step": round(res["store"]["ms"] / ms_fwd, 3),
+        "table_ops_per_adjoint": ops,
+        "pct_fp64_vector_peak_store": round(
+            100.0 * ops / (res["store"]["ms"] * 1e-3) / OC.FP64_VECTOR_PEAK, 4),
+        "store_equals_recompute": bool(torch.equal(grads["store"], grads["recompute"])),
+        "status": int(st.item()),
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -205,6 +299,12 @@ def main():
         if ev is not None:
             ev[3].record(stream)
 
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib << 17, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)   # reads and writes copy_mib MiB each
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -229,8 +329,9 @@ def main():
            "md_qr": OC.qr(N, N, M).table_ops(M),
            "md_series_solve": OC.series_solve(N, N, D).table_ops(M)}
     step_ops = sum(ops.values())
-    dom = max(dur, key=dur.get)
-    achieved = ops[dom] / (dur[dom] * 1e-3) / 1e12
+    # the dominant kernel is k_qr, md_qr's single launch (the solve is about
+    # 40 launches, the largest of them k_pinv_cols)
+    achieved = ops["md_qr"] / (dur["md_qr"] * 1e-3) / 1e12
     peak = OC.FP64_VECTOR_PEAK / 1e12
     value = 1000.0 / ms_per_step
     line = {
@@ -251,15 +352,18 @@ def main():
         "pct_fp64_vector_peak": round(100.0 * step_ops * value / OC.FP64_VECTOR_PEAK, 3),
         "table_ops_per_step": step_ops,
         "kernels_ms": {k: round(v, 4) for k, v in dur.items()},
-        "roofline": {"kernel": dom, "bound": "alu", "achieved": round(achieved, 4),
-                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 5),
-                     "traffic": None,
-                     "basis": "Table 1 hardware-double operations of the entry point's "
-                              "multiple-double operations per launch / mean launch time"},
+        "roofline": {"kernel": "k_qr (md_qr)", "bound": "alu", "achieved": round(achieved, 5),
+                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 6),
+                     "traffic": qr_traffic_bytes(),
+                     "basis": "Table 1 hardware-double operations of the QR's multiple-double "
+                              "operations per launch / mean launch time (HIP events); traffic: "
+                              "HBM bytes per launch from FETCH_SIZE + WRITE_SIZE, copy-scaled"},
         "status": st,
     }
     if not args.no_batched:
         line["batched"] = batched_measure(args, B, OC)
+    if not args.no_adjoint:
+        line["adjoint"] = adjoint_measure(args, B, OC)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(sysm, x_h, A_h, b_h, args.cpu_seconds)
     print(json.dumps(line), flush=True)

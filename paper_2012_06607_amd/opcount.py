@@ -185,3 +185,21 @@ def newton_step(sysm, d: int, m: int) -> Ops:
     o += _cabs2(L * sysm.n)    # |dx|^2
     o += sqrt_ops(m).scaled(2)
     return o
+
+
+def adjoint(sysm, d: int, m: int) -> Ops:
+    """Coefficient gradient through the converged series: evaluation and
+    differentiation at x, the QR of A_0, the transposed staggered
+    substitution (per stage A_0^H lambda_k = rhs_k through R^H and Q, and the
+    updates rhs_{k-j} -= A_j^H lambda_k: the same counts as the forward
+    solve), then per term and coefficient degree j the contraction
+    sum_{k=j}^{d} conj(m_{k-j}) lambda_k (the monomial series m are the
+    forward products, already counted in the evaluation)."""
+    o = eval_diff(sysm, d)
+    o += qr(sysm.N, sysm.n, m)
+    o += series_solve(sysm.N, sysm.n, d)
+    dcu = min(sysm.dc, d)
+    for j in range(dcu + 1):
+        o += _cmul(d + 1 - j).scaled(sysm.M)
+        o += _cadd(d - j).scaled(sysm.M)
+    return o
