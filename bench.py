@@ -134,15 +134,18 @@ def batched_measure(args, B, OC):
                  for sysm, x in paths if sysm.m == 4)
     batch = B.BatchedPaths(paths)
     stream = torch.cuda.current_stream()
-    B.md_newton_batch(batch, iters)           # warm up, then capture
+    from paper_2012_06607_amd.tune import tune_batch
+    tuned = tune_batch(batch, iters, stream=stream)
+    shape = {k: tuned["best"][k] for k in ("grid", "block", "eval_waves")}
+    B.md_newton_batch(batch, iters, stream=stream, **shape)   # warm up, then capture
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
-        B.md_newton_batch(batch, iters)
+        B.md_newton_batch(batch, iters, **shape)
     torch.cuda.synchronize()
     times = []
     for _ in range(args.batch_reps):
-        batch.reset(paths)
+        batch.restore()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -190,6 +193,9 @@ def batched_measure(args, B, OC):
         "speedup_vs_per_path_loop": round(ms_loop / ms, 2),
         "bitwise_equal_to_per_path": bool(same),
         "graph_replays": args.batch_reps,
+        "tuned_shape": {**shape, "order": tuned["best"]["order"]},
+        "tuner_trials": len(tuned["trials"]),
+        "slowest_path_ms": round(1e3 * tuned["path_seconds"]["max"], 3),
         "status": st,
     }
 

@@ -229,17 +229,31 @@ size_t md_batch_lds_bytes(int max_m, int max_d, int max_deg, int eval_waves);
 
 /* Runs `iters` Newton steps on each of `npaths` paths.  paths: device
  * md_path[npaths]; order: device int32[npaths], the order in which jobs are
- * handed out (a permutation of 0..npaths-1); counter: a device int32 used as the job counter
- * (reset by the call itself, on the stream, so the call can be captured in a
- * graph and replayed); status: device
- * int32[npaths], MD_ST_* bits per path, cleared by the caller; max_m, max_d,
- * max_deg: maxima over the paths (host values, they size the LDS); grid:
- * the number of resident workgroups (256 threads each); eval_waves (1..4):
- * waves per workgroup that evaluate terms.  Errors: MD_EINVAL, MD_ENULL,
- * MD_ESHAPE (LDS above 64 KiB), MD_EHIP. */
+ * handed out (a permutation of 0..npaths-1); counter: a device int32 used as
+ * the job counter (reset by the call itself, on the stream, so the call can
+ * be captured in a graph and replayed); status: device int32[npaths],
+ * MD_ST_* bits per path, cleared by the caller; max_m, max_d, max_deg:
+ * maxima over the paths (host values, they size the LDS); grid: the number
+ * of persistent workgroups; block: threads per workgroup, 256 or 512;
+ * eval_waves (1..block/64): waves per workgroup that evaluate terms;
+ * path_clock (may be NULL): device int64[2*npaths], receives for every path
+ * the device wall clock (md_wall_clock_hz ticks per second) when its
+ * workgroup took it and when it finished (for schedule tuning).
+ * Errors: MD_EINVAL, MD_ENULL, MD_ESHAPE (LDS above md_device_lds_bytes()),
+ * MD_EHIP. */
 int md_newton_batch(int npaths, const md_path *paths, const int32_t *order, const int32_t *ints,
                     double *reals, double *ws, int iters, int32_t *counter, int32_t *status,
-                    int max_m, int max_d, int max_deg, int grid, int eval_waves, void *stream);
+                    int max_m, int max_d, int max_deg, int grid, int block, int eval_waves,
+                    int64_t *path_clock, void *stream);
+
+/* Largest dynamic LDS in bytes that the kernels may take on the current
+ * device (the per-workgroup limit less 4 KiB for static LDS); bounds
+ * md_batch_lds_bytes for md_newton_batch. */
+size_t md_device_lds_bytes(void);
+
+/* Ticks per second of the device wall clock that md_newton_batch records,
+ * for `device`.  Errors: MD_ENULL, MD_EHIP. */
+int md_wall_clock_hz(int device, int64_t *hz);
 
 /* Message for the last error returned on this thread ("" if none). */
 const char *md_last_error(void);

@@ -381,6 +381,7 @@ class BatchedPaths:
         self.paths_dev = torch.as_tensor(table.view(np.uint8).copy(), device=dev)
         self.ints = torch.as_tensor(np.concatenate(ints) if ints else np.zeros(1, np.int32), device=dev)
         self.reals = torch.as_tensor(np.concatenate(reals) if reals else np.zeros(1), device=dev)
+        self.reals0 = self.reals.clone()  # start values, for restore()
         ws = torch.empty(n_ws + 32, dtype=torch.float64, device=dev)
         off = ((-ws.data_ptr()) % 256) // 8
         self.ws = ws[off:off + max(n_ws, 1)]
@@ -400,6 +401,19 @@ class BatchedPaths:
         o = int(self.table[p]["dx_norm"])
         return self.reals[o:o + 2 * m].view(m, 2)
 
+    def restore(self):
+        """Put the start series back from the device copy taken at
+        construction and clear the status (device work only)."""
+        self.reals.copy_(self.reals0)
+        self.status.zero_()
+
+    def set_order(self, order):
+        """Job order (a permutation of the paths)."""
+        order = np.asarray(order, dtype=np.int32)
+        if sorted(order.tolist()) != list(range(self.npaths)):
+            raise MdError("order must be a permutation of the paths")
+        self.order = torch.as_tensor(order, device=self.order.device)
+
     def reset(self, paths):
         """Put the start series back (same structure as at construction)."""
         for p, (_, x) in enumerate(paths):
@@ -415,24 +429,44 @@ def md_batch_lds_bytes(max_m: int, max_d: int, max_deg: int, eval_waves: int) ->
 
 
 def md_newton_batch(batch: BatchedPaths, iters: int, grid: int | None = None,
-                    eval_waves: int | None = None, stream=None):
+                    eval_waves: int | None = None, stream=None, block: int = 256,
+                    path_clock: torch.Tensor | None = None):
     """`iters` Newton steps on every path of the batch in one persistent
-    launch (the library resets the job counter on the stream first)."""
+    launch (the library resets the job counter on the stream first).
+    path_clock: optional int64 device tensor (npaths, 2) that receives each
+    path's start and end on the device wall clock."""
     L = lib()
     P, i32 = ctypes.c_void_p, ctypes.c_int
-    L.md_newton_batch.argtypes = [i32, P, P, P, P, P, i32, P, P, i32, i32, i32, i32, i32, P]
+    L.md_newton_batch.argtypes = [i32, P, P, P, P, P, i32, P, P, i32, i32, i32, i32, i32, i32, P, P]
     L.md_newton_batch.restype = ctypes.c_int
     if eval_waves is None:
         eval_waves = 4
         while eval_waves > 1 and md_batch_lds_bytes(batch.max_m, batch.max_d, batch.max_deg,
-                                                     eval_waves) > 64 * 1024:
+                                                     eval_waves) > md_device_lds_bytes():
             eval_waves -= 1
     if grid is None:
         props = torch.cuda.get_device_properties(batch.reals.device)
         grid = 2 * props.multi_processor_count
+    if path_clock is not None and tuple(path_clock.shape) != (batch.npaths, 2):
+        raise MdError("path_clock must have shape (npaths, 2)")
     _check(L.md_newton_batch(batch.npaths, _ptr(batch.paths_dev, torch.uint8), _ptr(batch.order, torch.int32),
                              _ptr(batch.ints, torch.int32), _ptr(batch.reals), _ptr(batch.ws),
                              iters, _ptr(batch.counter, torch.int32), _ptr(batch.status, torch.int32),
-                             batch.max_m, batch.max_d, batch.max_deg, grid, eval_waves,
-                             _stream(stream)), "md_newton_batch")
+                             batch.max_m, batch.max_d, batch.max_deg, grid, block, eval_waves,
+                             _ptr(path_clock, torch.int64), _stream(stream)), "md_newton_batch")
     return batch
+
+
+def md_device_lds_bytes() -> int:
+    L = lib()
+    L.md_device_lds_bytes.argtypes = []
+    L.md_device_lds_bytes.restype = ctypes.c_size_t
+    return int(L.md_device_lds_bytes())
+
+
+def md_wall_clock_hz(device: int = 0) -> int:
+    L = lib()
+    L.md_wall_clock_hz.argtypes = [ctypes.c_int, ctypes.c_void_p]
+    hz = ctypes.c_int64(0)
+    _check(L.md_wall_clock_hz(device, ctypes.byref(hz)), "md_wall_clock_hz")
+    return int(hz.value)

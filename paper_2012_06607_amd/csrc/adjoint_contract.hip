@@ -28,7 +28,7 @@ int contract_recompute_enqueue(int m, const EvalArgs &a, const double *lam, doub
     constexpr int Mm = decltype(Mc)::value;
     const size_t lds =
         sizeof(double) * 2 * Mm * size_t(2 * (a.Dmax > 0 ? a.Dmax : 1)) * (a.d + 1);
-    if (lds > 64 * 1024)
+    if (lds > lds_limit())
       return fail(MD_ESHAPE, "md_newton_adjoint: recomputing needs %zu bytes of LDS", lds);
     k_adj_contract_recompute<Mm><<<dim3(a.Mt), dim3(64), lds, s>>>(a, eval_group(a.d), lam, grad);
     return check_launch("md_newton_adjoint (contraction)");

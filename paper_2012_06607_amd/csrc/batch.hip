@@ -42,12 +42,12 @@ __device__ mdr<M> wg_max(mdr<M> v, mdr<M> *sh) {
 }
 
 template <int M>
-__device__ void newton_path(const md_path &p, int iters, const int32_t *__restrict__ ints,
+__device__ __forceinline__ void newton_path(const md_path &p, int iters, const int32_t *__restrict__ ints,
                             double *__restrict__ reals, double *__restrict__ wsb,
                             int32_t *__restrict__ status, int path, double *lds_raw,
                             int eval_waves) {
   __shared__ QrShared<M> qsh;
-  __shared__ mdr<M> msh[16];
+  __shared__ mdr<M> msh[16];  // one per wave, up to 1024 threads
   const int N = p.N, n = p.n, d = p.d, L = d + 1;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int wave = tid / WAVE, nwaves = nt / WAVE;
@@ -83,9 +83,11 @@ __device__ void newton_path(const md_path &p, int iters, const int32_t *__restri
   a.f = f;
   a.A = A;
   const int seg = N >= WAVE ? WAVE : pow2_at_least(N);
-  const int seg_up = n >= WAVE ? WAVE : pow2_at_least(n);
+  const int seg_dx = dot_seg(N), seg_up = dot_seg(n);
   const int spw = WAVE / seg, nslots = nwaves * spw;
   const int slot = wave * spw + lane_id() / seg;
+  const int spw_x = WAVE / seg_dx, nslots_x = nwaves * spw_x;
+  const int slot_x = wave * spw_x + lane_id() / seg_dx;
   const int spw_u = WAVE / seg_up, nslots_u = nwaves * spw_u;
   const int slot_u = wave * spw_u + lane_id() / seg_up;
   const int rgrp = eval_group(d);
@@ -113,9 +115,9 @@ __device__ void newton_path(const md_path &p, int iters, const int32_t *__restri
     __syncthreads();
     // staggered substitution
     for (int k = 0; k <= d; ++k) {
-      for (int base = 0; base < n; base += nslots) {
-        const int i = base + slot;
-        stage_dx_row<M>(i < n, i, k, N, n, d, seg, W, r, dx, st);
+      for (int base = 0; base < n; base += nslots_x) {
+        const int i = base + slot_x;
+        stage_dx_row<M>(i < n, i, k, N, n, d, seg_dx, W, r, dx, st);
       }
       __syncthreads();
       if (k < d) {
@@ -149,13 +151,14 @@ __device__ void newton_path(const md_path &p, int iters, const int32_t *__restri
 
 __global__ void k_reset_counter(int32_t *counter) { atomicExch(counter, 0); }
 
-__global__ void __launch_bounds__(256) k_newton_batch(int npaths, const md_path *__restrict__ paths,
-                                                      const int32_t *__restrict__ order,
-                                                      const int32_t *__restrict__ ints,
-                                                      double *__restrict__ reals,
-                                                      double *__restrict__ wsb, int iters,
-                                                      int32_t *counter, int32_t *status,
-                                                      int eval_waves) {
+template <int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_newton_batch(int npaths, const md_path *__restrict__ paths,
+                                                        const int32_t *__restrict__ order,
+                                                        const int32_t *__restrict__ ints,
+                                                        double *__restrict__ reals,
+                                                        double *__restrict__ wsb, int iters,
+                                                        int32_t *counter, int32_t *status,
+                                                        int eval_waves, int64_t *clk) {
   extern __shared__ double lds_raw[];
   __shared__ int sh_job;
   while (true) {
@@ -171,6 +174,7 @@ __global__ void __launch_bounds__(256) k_newton_batch(int npaths, const md_path 
       if (threadIdx.x == 0) atomicOr(status + path, MD_ST_BADPATH);
       continue;
     }
+    if (clk && threadIdx.x == 0) clk[2 * path] = wall_clock64();
     switch (p.m) {
       case 1: newton_path<1>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves); break;
       case 2: newton_path<2>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves); break;
@@ -180,6 +184,7 @@ __global__ void __launch_bounds__(256) k_newton_batch(int npaths, const md_path 
         if (threadIdx.x == 0) atomicOr(status + path, MD_ST_BADPATH);
         break;
     }
+    if (clk && threadIdx.x == 0) clk[2 * path + 1] = wall_clock64();
   }
 }
 
@@ -196,19 +201,38 @@ extern "C" size_t md_batch_lds_bytes(int max_m, int max_d, int max_deg, int eval
 extern "C" int md_newton_batch(int npaths, const md_path *paths, const int32_t *order,
                                const int32_t *ints, double *reals, double *ws, int iters,
                                int32_t *counter, int32_t *status, int max_m, int max_d,
-                               int max_deg, int grid, int eval_waves, void *stream) {
-  if (npaths < 0 || iters < 0 || grid < 1 || eval_waves < 1 || eval_waves > 4)
-    return fail(MD_EINVAL, "md_newton_batch: npaths=%d iters=%d grid=%d eval_waves=%d", npaths,
-                iters, grid, eval_waves);
+                               int max_deg, int grid, int block, int eval_waves,
+                               int64_t *path_clock, void *stream) {
+  if (npaths < 0 || iters < 0 || grid < 1 || (block != 256 && block != 512) || eval_waves < 1 ||
+      eval_waves > block / WAVE)
+    return fail(MD_EINVAL, "md_newton_batch: npaths=%d iters=%d grid=%d block=%d eval_waves=%d",
+                npaths, iters, grid, block, eval_waves);
   if (npaths == 0) return MD_OK;
   if (!paths || !order || !ints || !reals || !ws || !counter || !status)
     return fail(MD_ENULL, "md_newton_batch: null pointer");
   const size_t lds = md_batch_lds_bytes(max_m, max_d, max_deg, eval_waves);
   if (lds == 0) return fail(MD_EINVAL, "md_newton_batch: max_m=%d must be in 1..4", max_m);
-  if (lds > 64 * 1024)
-    return fail(MD_ESHAPE, "md_newton_batch: %zu bytes of LDS for the evaluation exceed 64 KiB", lds);
-  k_reset_counter<<<dim3(1), dim3(1), 0, (hipStream_t)stream>>>(counter);
-  k_newton_batch<<<dim3(grid), dim3(256), lds, (hipStream_t)stream>>>(
-      npaths, paths, order, ints, reals, ws, iters, counter, status, eval_waves);
+  if (lds > lds_limit())
+    return fail(MD_ESHAPE, "md_newton_batch: %zu bytes of LDS for the evaluation exceed %zu", lds,
+                lds_limit());
+  hipStream_t s = (hipStream_t)stream;
+  k_reset_counter<<<dim3(1), dim3(1), 0, s>>>(counter);
+  if (block == 256)
+    k_newton_batch<256><<<dim3(grid), dim3(256), lds, s>>>(npaths, paths, order, ints, reals, ws,
+                                                           iters, counter, status, eval_waves,
+                                                           path_clock);
+  else
+    k_newton_batch<512><<<dim3(grid), dim3(512), lds, s>>>(npaths, paths, order, ints, reals, ws,
+                                                           iters, counter, status, eval_waves,
+                                                           path_clock);
   return check_launch("md_newton_batch");
+}
+
+extern "C" int md_wall_clock_hz(int device, int64_t *hz) {
+  if (!hz) return fail(MD_ENULL, "md_wall_clock_hz: null pointer");
+  int khz = 0;
+  const hipError_t e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device);
+  if (e != hipSuccess) return fail(MD_EHIP, "md_wall_clock_hz: %s", hipGetErrorString(e));
+  *hz = int64_t(khz) * 1000;
+  return MD_OK;
 }

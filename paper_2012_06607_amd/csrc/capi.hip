@@ -30,7 +30,23 @@ int check_launch(const char *what) {
   return MD_OK;
 }
 
+size_t lds_limit() {
+  static size_t cache[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 65536 - 4096;
+  if (cache[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        v < 65536)
+      v = 65536;
+    cache[dev] = size_t(v) - 4096;
+  }
+  return cache[dev];
+}
+
 }  // namespace mds
+
+extern "C" size_t md_device_lds_bytes(void) { return mds::lds_limit(); }
 
 extern "C" const char *md_last_error(void) { return mds::g_err; }
 

@@ -19,6 +19,11 @@ int fail(int code, const char *fmt, ...);
 // check a launch; returns MD_OK or MD_EHIP
 int check_launch(const char *what);
 
+// Largest dynamic LDS (bytes) a kernel of this library may request on the
+// current device: the device's per-workgroup limit less 4 KiB kept for the
+// kernels' static LDS (65536 - 4096 if the attribute cannot be read).
+size_t lds_limit();
+
 inline bool valid_m(int m) {
   return m == 1 || m == 2 || m == 3 || m == 4 || m == 5 || m == 8 || m == 10;
 }

@@ -150,7 +150,7 @@ int eval_diff_enqueue(int m, int d, const md_system &sys, const double *x, doubl
     constexpr int Mm = decltype(Mc)::value;
     if (sys.M > 0) {
       const size_t lds = sizeof(double) * 2 * Mm * size_t(term_lds_series(sys.max_deg)) * (d + 1);
-      if (lds <= 64 * 1024) {
+      if (lds <= lds_limit()) {
         k_eval_terms_wave<Mm><<<dim3(sys.M), dim3(64), lds, s>>>(a, eval_group(d));
       } else {
         if (mono)

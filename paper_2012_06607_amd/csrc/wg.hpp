@@ -61,16 +61,117 @@ __device__ __forceinline__ mdr<M> rsqrt_doubling(const mdr<M> &a) {
 
 // ---------------------------------------------------------------------------
 // Householder QR by one workgroup (Section 4).  For column j: sigma (the
-// 2-norm from the diagonal down) and |alpha| from two waves, then
-// phi = alpha/|alpha|, v_j = (phi (|alpha| + sigma), tail), beta = 1/(sigma
-// (sigma + |alpha|)), R_jj = -phi sigma; every trailing column l gets
-// a_l -= beta (v^H a_l) v, one column per segment.
+// 2-norm from the diagonal down) and alpha = A[j][j] give phi = alpha/|alpha|,
+// v_j = (phi (|alpha| + sigma), tail), beta = 1/(sigma (sigma + |alpha|)),
+// R_jj = -phi sigma; every trailing column l gets a_l -= beta (v^H a_l) v,
+// one column per segment of lanes.
+//
+// Look-ahead: in step j, wave 0's first segment updates column j+1 and then,
+// from the values it still holds, forms reflector j+1, while the other
+// segments update the remaining columns (wave 0 takes no more than its
+// first round, so that the next reflector is ready as early as possible).
+// One barrier per column; the scalars of reflector j live in the LDS buffer
+// j & 1.
 
 template <int M>
 struct QrShared {
-  mdr<M> s2, ys, a2, ya, beta;
-  mdc<M> v0;
+  mdc<M> v0[2];
+  mdr<M> beta[2];
 };
+
+// Reflector j from the column values a segment holds (rows lis + r*seg): the
+// segment tree of |a_i|^2 over i >= j, alpha from the lane that holds row j;
+// lane 0 of the wave forms the scalars when `keep` (all lanes of the wave
+// call this; only the first segment's result is kept).
+template <int M, int RPL>
+__device__ __forceinline__ void qr_reflector(const mdc<M> (&col)[RPL], int j, int N, int n, int seg,
+                                             bool keep, QrShared<M> &sh, double *__restrict__ QR,
+                                             long E, double *__restrict__ vdiag,
+                                             double *__restrict__ beta, int &st) {
+  const int lane = lane_id();
+  const int lis = lane & (seg - 1);
+  mdr<M> s = md_zero<M>();
+  mdc<M> alpha = c_zero<M>();
+  bool first = true;
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int i = lis + r * seg;
+    if (i >= j && i < N) {
+      const mdr<M> t = c_abs2<M>(col[r]);
+      s = first ? t : md_add<M>(s, t);
+      first = false;
+    }
+    if (i == j) alpha = col[r];
+  }
+  s = seg_reduce_r<M>(s, seg);
+  alpha = shfl_c<M>(alpha, (lane & ~(seg - 1)) + (j & (seg - 1)));
+  if (keep && lane == 0) {
+    const mdr<M> s2 = s;
+    const mdr<M> a2 = c_abs2<M>(alpha);
+    const mdr<M> ys = rsqrt_doubling<M>(s2);
+    const mdr<M> ya = rsqrt_doubling<M>(a2);
+    const mdr<M> sigma = md_mul<M>(s2, ys);
+    mdr<M> aabs = md_mul<M>(a2, ya);
+    mdc<M> phi = c_zero<M>();
+    phi.re = md_from<M>(1.0);
+    if (a2.v[0] != 0.0) phi = c_mulr<M>(alpha, ya);
+    else aabs = md_zero<M>();
+    mdr<M> bet = md_zero<M>();
+    mdc<M> v0 = c_zero<M>(), rjj = c_zero<M>();
+    if (s2.v[0] == 0.0) {
+      st |= MD_ST_SINGULAR;
+    } else {
+      const mdr<M> sp = md_add<M>(aabs, sigma);
+      v0 = c_mulr<M>(phi, sp);
+      bet = md_div<M>(ys, sp);
+      rjj = c_neg<M>(c_mulr<M>(phi, sigma));
+    }
+    if (!c_finite<M>(rjj) || !md_finite<M>(bet)) st |= MD_ST_NONFINITE;
+    sh.v0[j & 1] = v0;
+    sh.beta[j & 1] = bet;
+    cstore<M>(vdiag, n, j, v0);
+    rstore<M>(beta, n, j, bet);
+    cstore<M>(QR, E, long(j) * n + j, rjj);
+  }
+}
+
+// a_l -= beta (v^H a_l) v over rows i >= j by one segment; `anew` receives
+// the updated values (zero outside rows j..N-1).  The diagonal entry of
+// column j+1 is not stored: its reflector's R_jj replaces it.
+template <int M, int RPL>
+__device__ __forceinline__ void qr_update_column(bool live, int l, int j, int N, int n, int seg,
+                                                 const mdc<M> (&vi)[RPL], const mdr<M> &bet,
+                                                 double *__restrict__ QR, long E,
+                                                 mdc<M> (&anew)[RPL]) {
+  const int lane = lane_id();
+  const int lis = lane & (seg - 1);
+  mdc<M> al[RPL];
+  mdc<M> w = c_zero<M>();
+  bool first = true;
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int i = lis + r * seg;
+    al[r] = c_zero<M>();
+    if (live && i >= j && i < N) {
+      al[r] = cload<M>(QR, E, long(i) * n + l);
+      const mdc<M> t = c_mul<M>(c_conj<M>(vi[r]), al[r]);
+      w = first ? t : c_add<M>(w, t);
+      first = false;
+    }
+  }
+  w = seg_reduce_c<M>(w, seg);
+  w = shfl_c<M>(w, lane & ~(seg - 1));
+  const mdc<M> bw = c_mulr<M>(w, bet);
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int i = lis + r * seg;
+    anew[r] = c_zero<M>();
+    if (live && i >= j && i < N) {
+      anew[r] = c_sub<M>(al[r], c_mul<M>(bw, vi[r]));
+      if (!(l == j + 1 && i == l)) cstore<M>(QR, E, long(i) * n + l, anew[r]);
+    }
+  }
+}
 
 template <int M, int RPL>
 __device__ __forceinline__ void qr_wg(QrShared<M> &sh, int N, int n, int seg, const double *__restrict__ A0,
@@ -84,93 +185,60 @@ __device__ __forceinline__ void qr_wg(QrShared<M> &sh, int N, int n, int seg, co
   const int spw = WAVE / seg;
   const int slot = wave * spw + lane / seg;
   const int nslots = nwaves * spw;
+  const int others = nslots - spw;  // slots outside wave 0
   for (long e = threadIdx.x; e < E; e += blockDim.x) cstore<M>(QR, E, e, cload<M>(A0, A0E, e));
   __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    if (wave == 0) {
-      mdr<M> s = md_zero<M>();
-      bool first = true;
-      if (lane < seg) {
-#pragma unroll
-        for (int r = 0; r < RPL; ++r) {
-          const int i = lis + r * seg;
-          if (i >= j && i < N) {
-            const mdr<M> t = c_abs2<M>(cload<M>(QR, E, long(i) * n + j));
-            s = first ? t : md_add<M>(s, t);
-            first = false;
-          }
-        }
-      }
-      s = seg_reduce_r<M>(s, seg);
-      if (lane == 0) {
-        sh.s2 = s;
-        sh.ys = rsqrt_doubling<M>(s);
-      }
-    }
-    if (wave == (nwaves > 1 ? 1 : 0) && lane == (nwaves > 1 ? 0 : 1)) {
-      const mdr<M> a2 = c_abs2<M>(cload<M>(QR, E, long(j) * n + j));
-      sh.a2 = a2;
-      sh.ya = rsqrt_doubling<M>(a2);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const mdc<M> alpha = cload<M>(QR, E, long(j) * n + j);
-      const mdr<M> s2 = sh.s2, ys = sh.ys, a2 = sh.a2, ya = sh.ya;
-      const mdr<M> sigma = md_mul<M>(s2, ys);
-      mdr<M> aabs = md_mul<M>(a2, ya);
-      mdc<M> phi = c_zero<M>();
-      phi.re = md_from<M>(1.0);
-      if (a2.v[0] != 0.0) phi = c_mulr<M>(alpha, ya);
-      else aabs = md_zero<M>();
-      mdr<M> bet = md_zero<M>();
-      mdc<M> v0 = c_zero<M>(), rjj = c_zero<M>();
-      if (s2.v[0] == 0.0) {
-        st |= MD_ST_SINGULAR;
-      } else {
-        const mdr<M> sp = md_add<M>(aabs, sigma);
-        v0 = c_mulr<M>(phi, sp);
-        bet = md_div<M>(ys, sp);
-        rjj = c_neg<M>(c_mulr<M>(phi, sigma));
-      }
-      if (!c_finite<M>(rjj) || !md_finite<M>(bet)) st |= MD_ST_NONFINITE;
-      sh.v0 = v0;
-      sh.beta = bet;
-      cstore<M>(vdiag, n, j, v0);
-      rstore<M>(beta, n, j, bet);
-      cstore<M>(QR, E, long(j) * n + j, rjj);
-    }
-    __syncthreads();
-    const mdc<M> v0 = sh.v0;
-    const mdr<M> bet = sh.beta;
-    const int ncols = n - j - 1;
-    for (int base = 0; base < ncols; base += nslots) {
-      const int l = j + 1 + base + slot;
-      const bool live = l < n;
-      mdc<M> vi[RPL], al[RPL];
-      mdc<M> w = c_zero<M>();
-      bool first = true;
+  // step j = -1 only loads column 0 and forms reflector 0
+  for (int j = -1; j < n; ++j) {
+    mdc<M> vi[RPL], anew[RPL];
+    mdr<M> bet = md_zero<M>();
+    if (j >= 0) {
+      const mdc<M> v0 = sh.v0[j & 1];
+      bet = sh.beta[j & 1];
 #pragma unroll
       for (int r = 0; r < RPL; ++r) {
         const int i = lis + r * seg;
         vi[r] = c_zero<M>();
-        al[r] = c_zero<M>();
-        if (live && i >= j && i < N) {
-          vi[r] = (i == j) ? v0 : cload<M>(QR, E, long(i) * n + j);
-          al[r] = cload<M>(QR, E, long(i) * n + l);
-          const mdc<M> t = c_mul<M>(c_conj<M>(vi[r]), al[r]);
-          w = first ? t : c_add<M>(w, t);
-          first = false;
-        }
+        if (i == j) vi[r] = v0;
+        else if (i > j && i < N) vi[r] = cload<M>(QR, E, long(i) * n + j);
       }
-      w = seg_reduce_c<M>(w, seg);
-      w = shfl_c<M>(w, lane & ~(seg - 1));
-      const mdc<M> bw = c_mulr<M>(w, bet);
+    }
+    // Columns j+1.. go out round by round, one per slot.  Wave 0's first
+    // segment has column j+1 in round 0 and then forms reflector j+1 (worth
+    // about two rounds), so wave 0 stops after round k0 - 1 and the slots of
+    // the other waves take the columns that are left.
+    const int ncols = n - j - 1;
+    int k0 = 0, rounds = 0;
+    if (j < 0) {
+      k0 = 1;
+      rounds = wave == 0 ? 1 : 0;
+    } else if (ncols > 0) {
+      const int all = (ncols + nslots - 1) / nslots;
+      if (others == 0) {
+        k0 = all;
+        rounds = all;
+      } else {
+        const int kall = (ncols + 2 * spw + nslots - 1) / nslots;
+        k0 = kall > 3 ? kall - 2 : 1;
+        if (k0 > all) k0 = all;
+        const int rest = ncols - k0 * nslots;
+        rounds = wave == 0 ? k0 : k0 + (rest > 0 ? (rest + others - 1) / others : 0);
+      }
+    }
+    for (int k = 0; k < rounds; ++k) {
+      const int l = k < k0 ? j + 1 + k * nslots + slot
+                           : j + 1 + k0 * nslots + (k - k0) * others + (slot - spw);
+      if (j < 0) {
 #pragma unroll
-      for (int r = 0; r < RPL; ++r) {
-        const int i = lis + r * seg;
-        if (live && i >= j && i < N)
-          cstore<M>(QR, E, long(i) * n + l, c_sub<M>(al[r], c_mul<M>(bw, vi[r])));
+        for (int r = 0; r < RPL; ++r) {
+          const int i = lis + r * seg;
+          anew[r] = (l < n && i < N) ? cload<M>(QR, E, long(i) * n + l) : c_zero<M>();
+        }
+      } else {
+        qr_update_column<M, RPL>(l < n, l, j, N, n, seg, vi, bet, QR, E, anew);
       }
+      if (k == 0 && wave == 0 && j + 1 < n)
+        qr_reflector<M, RPL>(anew, j + 1, N, n, seg, true, sh, QR, E, vdiag, beta, st);
     }
     __syncthreads();
   }
@@ -257,6 +325,15 @@ __device__ __forceinline__ void pinv_column(bool live, int c, int N, int n, int 
       if (i < n) cstore<M>(W, EW, long(i) * N + c, g[r]);
     }
   }
+}
+
+// Lanes per dot product of the staggered stages (length len): each lane sums
+// up to four products in sequence, then a segment tree adds the lanes.  The
+// choice depends on the length only, so the single-path kernels and the
+// batched kernel sum in the same order.
+__host__ __device__ inline int dot_seg(int len) {
+  const int s = pow2_at_least((len + 3) / 4);
+  return s > WAVE ? WAVE : s;
 }
 
 // dx_k[i] = sum_c W[i][c] r_k[c] by one segment

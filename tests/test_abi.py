@@ -113,18 +113,21 @@ def test_adjoint_host_checks(lib):
 def test_batch_host_checks(lib):
     P = ctypes.c_void_p
     i = ctypes.c_int
-    lib.md_newton_batch.argtypes = [i, P, P, P, P, P, i, P, P, i, i, i, i, i, P]
+    lib.md_newton_batch.argtypes = [i, P, P, P, P, P, i, P, P, i, i, i, i, i, i, P, P]
     lib.md_batch_lds_bytes.argtypes = [i] * 4
     lib.md_batch_lds_bytes.restype = ctypes.c_size_t
     fake = P(4096)
     args = [fake] * 5
     # penta double paths are not carried by the batched kernel: rejected on the host
-    assert lib.md_newton_batch(4, *args, 1, fake, fake, 5, 8, 3, 16, 4, None) == 1
-    assert lib.md_newton_batch(4, *args, 1, fake, fake, 4, 8, 3, 0, 4, None) == 1     # grid 0
-    assert lib.md_newton_batch(4, *args, 1, fake, fake, 4, 8, 3, 16, 5, None) == 1    # eval waves
-    assert lib.md_newton_batch(4, None, *args[1:], 1, fake, fake, 4, 8, 3, 16, 4, None) == 3
-    assert lib.md_newton_batch(0, *args, 1, fake, fake, 4, 8, 3, 16, 4, None) == 0    # empty batch
+    assert lib.md_newton_batch(4, *args, 1, fake, fake, 5, 8, 3, 16, 256, 4, None, None) == 1
+    assert lib.md_newton_batch(4, *args, 1, fake, fake, 4, 8, 3, 0, 256, 4, None, None) == 1   # grid 0
+    assert lib.md_newton_batch(4, *args, 1, fake, fake, 4, 8, 3, 16, 256, 5, None, None) == 1  # eval waves
+    assert lib.md_newton_batch(4, *args, 1, fake, fake, 4, 8, 3, 16, 512, 9, None, None) == 1
+    assert lib.md_newton_batch(4, *args, 1, fake, fake, 4, 8, 3, 16, 384, 4, None, None) == 1  # block
+    assert lib.md_newton_batch(4, None, *args[1:], 1, fake, fake, 4, 8, 3, 16, 256, 4, None,
+                               None) == 3
+    assert lib.md_newton_batch(0, *args, 1, fake, fake, 4, 8, 3, 16, 256, 4, None, None) == 0
     # evaluation LDS above 64 KiB is refused (deca-size series on 4 waves)
     assert lib.md_batch_lds_bytes(4, 200, 4, 4) > 64 * 1024
-    assert lib.md_newton_batch(4, *args, 1, fake, fake, 4, 200, 4, 16, 4, None) == 2
+    assert lib.md_newton_batch(4, *args, 1, fake, fake, 4, 200, 4, 16, 256, 4, None, None) == 2
     assert lib.md_batch_lds_bytes(5, 8, 3, 4) == 0

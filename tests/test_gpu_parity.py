@@ -390,8 +390,16 @@ def test_batch_against_oracle_and_reruns(B):
     first = [host(batch.x(p)).copy() for p in range(len(paths))]
     batch.reset(paths)
     B.md_newton_batch(batch, 2, grid=7, eval_waves=1)
+    second = [host(batch.x(p)).copy() for p in range(len(paths))]
+    batch.restore()
+    batch.set_order(np.arange(len(paths))[::-1])
+    clk = torch.zeros((len(paths), 2), dtype=torch.int64, device="cuda")
+    B.md_newton_batch(batch, 2, grid=5, block=512, eval_waves=8, path_clock=clk)
+    c = host(clk)
+    assert np.all(c[:, 0] > 0) and np.all(c[:, 1] >= c[:, 0])
     for p, (sysm, x) in enumerate(paths):
-        assert np.array_equal(host(batch.x(p)), first[p])   # schedule does not change bits
+        # neither the launch shape nor the job order changes the bits
+        assert np.array_equal(second[p], first[p]) and np.array_equal(host(batch.x(p)), first[p])
         xw = x
         for _ in range(2):
             xw, _, _ = oracle.newton_step(sysm, xw)
