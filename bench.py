@@ -1,26 +1,26 @@
 #!/usr/bin/env python3
 """Throughput of the multiple-double series Newton path on one MI355X.
 
-Workload (quad double, complex; the 32-unknown, degree-16 configuration):
-one step is
-  * md_poly_eval_diff: a 32 x 32 polynomial system, 16 monomials of degree
-    <= 4 per equation, unit complex coefficients, at a series point with
-    unit complex coefficients, truncation degree d = 16;
-  * md_qr: Householder QR of A_0 (32 x 32, A_0 = U diag(s) U^H with
-    condition number 1e3);
-  * md_series_solve: the staggered solve of A(t) dx(t) = b(t), d = 16, with
-    A_1..A_16 and b unit complex,
-i.e. the kernels of one Newton step at this size.  Inputs are seeded,
-synthetic and resident in HBM before timing.
+Headline workload (one "step" = one pass over one batch of paths): 1024
+independent paths, n uniform in {8, 16, ..., 64}, d uniform in 8..32, half
+double double and half quad double, each a system of n equations with 8
+monomials of degree <= 3, a constant and a t-term per equation and a root
+at t = 0, 4 Newton steps per path (evaluation and differentiation, QR of
+A_0, staggered solve, update), all in one persistent launch captured in a
+graph.  Inputs are seeded, synthetic and resident in HBM before timing.
+The value is Newton steps per second (paths x 4 per launch / launch time).
 
-Prints one JSON line: steps/s, the fraction of the FP64 vector peak reached
-by the step's algorithmic work (Table 1 operation counts), the roofline of
-the dominant kernel, and the CPU oracle timed on the host on the same
-inputs.
+The same JSON line also carries: the roofline of the launch's only kernel
+(Table 1 operations per launch against the FP64 vector peak, and its HBM
+traffic from hardware counters), the per-path launch loop on the same
+paths, the single 32-unknown quad-double step (eval + QR + solve), the
+adjoint of a converged 32-unknown quad-double series, and the CPU oracle
+timed on a sample of the same paths.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -31,52 +31,59 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "multiple-double series Newton steps/s and % of FP64 vector peak"
-M, N, D = 4, 32, 16
-WORKLOAD = ("qd complex, n=N=32, d=16: eval/diff of a 32x32 system (16 monomials of degree<=4 "
-            "per equation) + Householder QR of A0 (cond 1e3) + staggered block Toeplitz solve")
+ITERS = 4
+WORKLOAD = ("1024 paths, n in {8,...,64}, d in 8..32, half double double / half quad double, "
+            "8 monomials of degree <= 3 + constant + t-term per equation, 4 Newton steps per "
+            "path, one persistent launch in a graph")
+M1, N1, D1 = 4, 32, 16    # the single-path step
 
-
-# HBM traffic of one k_qr launch (quad double, 32 x 32) from two rocprofv3
-# --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch,
-# mean over the dispatches), each scaled by what the same counter reads for
-# a plain 256 MiB device copy in the same run (--copy-mib 256: FETCH_SIZE
-# read 131088 KiB for 262144 KiB moved, WRITE_SIZE 262147 KiB).  Valid only
-# for the kernel sources it was taken on: the figure is dropped when their
-# hash differs.
-QR_TRAFFIC = {
-    "fetch_kib": 134.6, "fetch_scale": 262144 / 131088.2,
-    "write_kib": 67.0, "write_scale": 262144 / 262146.8,
-    "sources": ("qr.hip", "internal.hpp", "common.hpp", "md.hpp", "wg.hpp", "layout.hpp",
-                "series.hpp"),
-    "sha256": "bb15957c50d71f61492f439d6df4a31e341a42d7dcb59a18a121cf51a64081f9",
+# HBM traffic of one launch from two rocprofv3 --pmc runs of this script
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
+# same counter reads for a plain 256 MiB device copy in the same run
+# (--copy-mib 256).  Valid only for the kernel sources the counters were
+# taken on: dropped (null) when their hash differs.
+TRAFFIC = {
+    "k_newton_batch": {"fetch_kib": None, "fetch_scale": None, "write_kib": None,
+                       "write_scale": None, "sha256": "",
+                       "sources": ("batch.hip", "internal.hpp", "common.hpp", "md.hpp", "wg.hpp",
+                                   "layout.hpp", "series.hpp")},
+    "k_qr": {"fetch_kib": 134.6, "fetch_scale": 262144 / 131088.2, "write_kib": 67.0,
+             "write_scale": 262144 / 262146.8,
+             "sha256": "bb15957c50d71f61492f439d6df4a31e341a42d7dcb59a18a121cf51a64081f9",
+             "sources": ("qr.hip", "internal.hpp", "common.hpp", "md.hpp", "wg.hpp",
+                         "layout.hpp", "series.hpp")},
 }
 
 
-def qr_traffic_bytes():
-    """k_qr's measured HBM bytes per launch, or None once its sources changed."""
-    import hashlib
+def traffic_bytes(kernel: str):
+    """Measured HBM bytes per launch, or None once the kernel's sources changed."""
+    t = TRAFFIC[kernel]
+    if t["fetch_kib"] is None:
+        return None
     h = hashlib.sha256()
-    for name in QR_TRAFFIC["sources"]:
+    for name in t["sources"]:
         with open(os.path.join(ROOT, "paper_2012_06607_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest() != QR_TRAFFIC["sha256"]:
+    if h.hexdigest() != t["sha256"]:
         return None
-    t = QR_TRAFFIC
     return int(round(1024 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])))
 
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=5, help="timed launches (graph replays)")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--paths", type=int, default=1024)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall time budget of the CPU oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batched", action="store_true",
-                    help="skip the batched-paths measurement (1024 paths, one persistent launch)")
-    ap.add_argument("--batch-paths", type=int, default=1024)
-    ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the launch-shape tuner (512 threads, one workgroup per CU)")
+    ap.add_argument("--no-loop", action="store_true", help="skip the per-path launch loop")
+    ap.add_argument("--no-single", action="store_true",
+                    help="skip the single-path step (32 unknowns, d = 16, quad double)")
+    ap.add_argument("--single-steps", type=int, default=50)
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint measurement (32 unknowns, d = 16, quad double)")
     ap.add_argument("--adj-reps", type=int, default=20)
@@ -86,65 +93,71 @@ def parse():
     return ap.parse_args()
 
 
-def make_inputs():
+def make_paths(count):
     from paper_2012_06607_amd import inputs as I
-    sysm = I.eval_system((2, 0), N, N, M, 16, 4)
-    x = I.unit_series((2, 1), M, D, N)
-    A, b = I.toeplitz_system((2, N), N, D, M)
-    return sysm, x, A, b
-
-
-def cpu_baseline(sysm, x, A, b, budget_s: float) -> dict:
-    """The oracle, single threaded, on the same inputs: full steps until the
-    time budget is spent."""
-    import oracle
-    oracle.build()
-    t0 = time.perf_counter()
-    steps = 0
-    while True:
-        oracle.eval_diff(sysm, x)
-        QR, vd, beta, _ = oracle.qr(A[:, :, 0])
-        oracle.series_solve(QR, vd, beta, A, b)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s:
-            break
-    return {"value": steps / el, "unit": "steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} full steps of the same workload on one host thread "
-                      f"({el:.1f} s, gcc -O2 C oracle)"}
-
-
-def batched_measure(args, B, OC):
-    """1024 independent paths (n in {8,...,64}, d in 8..32, half double double,
-    half quad double, systems of 8 monomials of degree <= 3 per equation with
-    a root at t = 0), 4 Newton steps each: one persistent launch captured in a
-    graph and replayed, against the per-path launch loop on the same GPU."""
-    import numpy as np
-    import torch
-    from paper_2012_06607_amd import inputs as I
-    iters = 4
-    specs = I.batch_specs((4, 0), args.batch_paths)
+    specs = I.batch_specs((4, 0), count)
     paths = []
     for sp in specs:
         sysm, x0 = I.newton_system((4, sp.path), sp.n, sp.m)
         paths.append((sysm, I.series_start(x0, sp.d)))
-    ops = sum(iters * OC.newton_step(sysm, x.shape[2] - 1, sysm.m).table_ops(sysm.m)
-              for sysm, x in paths)
-    ops_qd = sum(iters * OC.newton_step(sysm, x.shape[2] - 1, sysm.m).table_ops(sysm.m)
-                 for sysm, x in paths if sysm.m == 4)
+    return paths
+
+
+def cpu_baseline(paths, budget_s: float) -> dict:
+    """The oracle, single threaded, on a sample of the same paths (every
+    path in turn from a stride through the batch, 4 Newton steps each)
+    until the time budget is spent; Newton steps per second."""
+    import oracle
+    oracle.build()
+    stride = 37                           # coprime with the batch size: mixes n, d, m
+    t0 = time.perf_counter()
+    steps, done = 0, []
+    p = 0
+    while True:
+        sysm, x = paths[p % len(paths)]
+        oracle.newton(sysm, x, ITERS)
+        steps += ITERS
+        done.append(p % len(paths))
+        p += stride
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    ns = sorted({paths[q][0].n for q in done})
+    return {"value": round(steps / el, 3), "unit": "Newton steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(done)} paths of the batch (every {stride}th, n in {ns}), "
+                      f"{ITERS} Newton steps each, {el:.1f} s on one host thread, gcc -O2 C oracle"}
+
+
+def batched(args, B, OC, paths):
+    import numpy as np
+    import torch
     batch = B.BatchedPaths(paths)
     stream = torch.cuda.current_stream()
-    from paper_2012_06607_amd.tune import tune_batch
-    tuned = tune_batch(batch, iters, stream=stream)
-    shape = {k: tuned["best"][k] for k in ("grid", "block", "eval_waves")}
-    B.md_newton_batch(batch, iters, stream=stream, **shape)   # warm up, then capture
+    ops = sum(ITERS * OC.newton_step(sysm, x.shape[2] - 1, sysm.m).table_ops(sysm.m)
+              for sysm, x in paths)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    if args.no_tune:
+        shape = {"grid": cus, "block": 512, "eval_waves": 8}
+        while shape["eval_waves"] > 1 and B.md_batch_lds_bytes(
+                batch.max_m, batch.max_d, batch.max_deg, shape["eval_waves"]) > B.md_device_lds_bytes():
+            shape["eval_waves"] -= 1
+        tuned = None
+    else:
+        from paper_2012_06607_amd.tune import tune_batch
+        tuned = tune_batch(batch, ITERS, stream=stream)
+        shape = {k: tuned["best"][k] for k in ("grid", "block", "eval_waves")}
+    B.md_newton_batch(batch, ITERS, stream=stream, **shape)
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
-        B.md_newton_batch(batch, iters, **shape)
+        B.md_newton_batch(batch, ITERS, **shape)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        batch.restore()
+        g.replay()
     torch.cuda.synchronize()
     times = []
-    for _ in range(args.batch_reps):
+    for _ in range(args.steps):
         batch.restore()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -153,54 +166,119 @@ def batched_measure(args, B, OC):
         e1.record(stream)
         torch.cuda.synchronize()
         times.append(e0.elapsed_time(e1))
-    ms = float(np.median(times))
-    st = int(batch.status.max().item())
-    # the per-path launch loop on the same paths
-    sds = [B.DeviceSystem(sysm) for sysm, _ in paths]
-    xs = [torch.as_tensor(x, device="cuda") for _, x in paths]
-    wss = [B.workspace(B.MD_FN_NEWTON, sysm.m, sysm.N, sysm.n, x.shape[2] - 1, sysm.M,
-                       sysm.max_deg) for sysm, x in paths]
-    stat = torch.zeros(1, dtype=torch.int32, device="cuda")
-    nrm = [torch.empty((sysm.m, 2), dtype=torch.float64, device="cuda") for sysm, _ in paths]
+    ms = float(np.mean(times))
+    res = {"ms": ms, "ops": ops, "shape": shape, "times": times,
+           "status": int(batch.status.max().item()), "tuned": tuned, "batch": batch,
+           "qd_share": sum(ITERS * OC.newton_step(s, x.shape[2] - 1, s.m).table_ops(s.m)
+                           for s, x in paths if s.m == 4) / ops}
+    if not args.no_loop:
+        sds = [B.DeviceSystem(sysm) for sysm, _ in paths]
+        xs = [torch.as_tensor(x, device="cuda") for _, x in paths]
+        wss = [B.workspace(B.MD_FN_NEWTON, sysm.m, sysm.N, sysm.n, x.shape[2] - 1, sysm.M,
+                           sysm.max_deg) for sysm, x in paths]
+        stat = torch.zeros(1, dtype=torch.int32, device="cuda")
+        nrm = [torch.empty((sysm.m, 2), dtype=torch.float64, device="cuda") for sysm, _ in paths]
 
-    def loop():
-        for p in range(len(paths)):
-            for _ in range(iters):
-                B.md_newton_step(sds[p], xs[p], nrm[p], wss[p], stat, stream)
-    loop()
+        def loop():
+            for p in range(len(paths)):
+                for _ in range(ITERS):
+                    B.md_newton_step(sds[p], xs[p], nrm[p], wss[p], stat, stream)
+        loop()
+        torch.cuda.synchronize()
+        for p, (_, x) in enumerate(paths):
+            xs[p].copy_(torch.as_tensor(x))
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        loop()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res["loop_ms"] = e0.elapsed_time(e1)
+        # largest difference between the two, per coefficient, relative to
+        # the coefficient vector's size, in units of 2^-(53m-8)
+        worst = 0.0
+        for p, (sysm, _) in enumerate(paths):
+            a, b = xs[p].cpu().numpy(), batch.x(p).cpu().numpy()
+            diff = np.abs((a - b).sum(axis=1)).max(axis=(0, 2))     # per k, limb sums
+            size = np.maximum(np.abs(a[:, 0]).max(axis=(0, 2)), 1e-300)
+            worst = max(worst, float((diff / size).max()) / 2.0 ** -(53 * sysm.m - 8))
+        res["diff_units"] = worst
+    return res
+
+
+def single_path(args, B, OC) -> dict:
+    """The 32-unknown quad-double step on one path: md_poly_eval_diff on a
+    32 x 32 system (16 monomials of degree <= 4 per equation) at a unit
+    series point, md_qr of a 32 x 32 A_0 with condition number 1e3, and
+    md_series_solve with d = 16."""
+    import numpy as np
+    import torch
+    from paper_2012_06607_amd import inputs as I
+    sysm = I.eval_system((2, 0), N1, N1, M1, 16, 4)
+    x = torch.as_tensor(I.unit_series((2, 1), M1, D1, N1), device="cuda")
+    A_h, b_h = I.toeplitz_system((2, N1), N1, D1, M1)
+    A = torch.as_tensor(A_h, device="cuda")
+    b = torch.as_tensor(b_h, device="cuda")
+    sd = B.DeviceSystem(sysm)
+    A0 = A[:, :, 0].contiguous()
+    f = torch.empty((2, M1, D1 + 1, N1), dtype=torch.float64, device="cuda")
+    Aev = torch.empty((2, M1, D1 + 1, N1, N1), dtype=torch.float64, device="cuda")
+    dx = torch.empty((2, M1, D1 + 1, N1), dtype=torch.float64, device="cuda")
+    ws_eval = B.workspace(B.MD_FN_EVAL, M1, N1, N1, D1, sysm.M, sysm.max_deg)
+    ws_solve = B.workspace(B.MD_FN_SOLVE, M1, N1, N1, D1, 0, 0)
+    QRb = torch.empty_like(A0)
+    vdb = torch.empty((2, M1, N1), dtype=torch.float64, device="cuda")
+    betab = torch.empty((M1, N1), dtype=torch.float64, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        B.md_poly_eval_diff(sd, x, f, Aev, ws_eval, stream)
+        if ev is not None:
+            ev[1].record(stream)
+        QR, vd, beta, _ = B.md_qr(A0, status, stream, QRb, vdb, betab)
+        if ev is not None:
+            ev[2].record(stream)
+        B.md_series_solve(QR, vd, beta, A, b, dx, ws_solve, status, stream)
+        if ev is not None:
+            ev[3].record(stream)
+
+    for _ in range(5):
+        step()
+    K = args.single_steps
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    for p, (_, x) in enumerate(paths):
-        xs[p].copy_(torch.as_tensor(x))
+    t0.record(stream)
+    for s in range(K):
+        step(evs[s])
+    t1.record(stream)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    loop()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_loop = e0.elapsed_time(e1)
-    same = all(torch.equal(xs[p], batch.x(p)) for p in range(len(paths)))
-    steps = len(paths) * iters
-    peak = OC.FP64_VECTOR_PEAK
+    ms = t0.elapsed_time(t1) / K
+    names = ("md_poly_eval_diff", "md_qr", "md_series_solve")
+    dur = {nm: float(np.mean([evs[s][i].elapsed_time(evs[s][i + 1]) for s in range(K)]))
+           for i, nm in enumerate(names)}
+    ops = {"md_poly_eval_diff": OC.eval_diff(sysm, D1).table_ops(M1),
+           "md_qr": OC.qr(N1, N1, M1).table_ops(M1),
+           "md_series_solve": OC.series_solve(N1, N1, D1).table_ops(M1)}
+    qr_tf = ops["md_qr"] / (dur["md_qr"] * 1e-3) / 1e12
     return {
-        "workload": f"{len(paths)} paths, n in 8..64 step 8, d in 8..32, half dd / half qd, "
-                    f"8 monomials of degree <= 3 per equation, {iters} Newton steps each",
-        "steps_per_s": round(steps / (ms * 1e-3), 2),
-        "ms_per_launch": round(ms, 3),
-        "table_ops_per_launch": ops,
-        "pct_fp64_vector_peak": round(100.0 * ops / (ms * 1e-3) / peak, 3),
-        "qd_share_of_ops": round(ops_qd / ops, 4),
-        "per_path_loop_ms": round(ms_loop, 3),
-        "speedup_vs_per_path_loop": round(ms_loop / ms, 2),
-        "bitwise_equal_to_per_path": bool(same),
-        "graph_replays": args.batch_reps,
-        "tuned_shape": {**shape, "order": tuned["best"]["order"]},
-        "tuner_trials": len(tuned["trials"]),
-        "slowest_path_ms": round(1e3 * tuned["path_seconds"]["max"], 3),
-        "status": st,
+        "workload": "qd, n = N = 32, d = 16: eval/diff of a 32x32 system (16 monomials of "
+                    "degree <= 4 per equation) + QR of A_0 (cond 1e3) + staggered solve",
+        "steps_per_s": round(1000.0 / ms, 3), "ms_per_step": round(ms, 4),
+        "pct_fp64_vector_peak": round(100.0 * sum(ops.values()) / (ms * 1e-3)
+                                      / OC.FP64_VECTOR_PEAK, 4),
+        "kernels_ms": {k: round(v, 4) for k, v in dur.items()},
+        "k_qr_roofline": {"bound": "alu", "achieved": round(qr_tf, 5), "peak": 78.6,
+                          "unit": "TFLOP/s", "frac": round(qr_tf / 78.6, 6),
+                          "traffic": traffic_bytes("k_qr")},
+        "status": int(status.item()),
     }
 
 
-def adjoint_measure(args, B, OC):
+def adjoint_measure(args, B, OC) -> dict:
     """Quad double series Newton on a 32-unknown system (8 monomials of degree
     <= 3, a constant and a t-term per equation: 320 coefficients), d = 16,
     8 steps from the root at t = 0; then the coefficient gradient of
@@ -232,8 +310,7 @@ def adjoint_measure(args, B, OC):
     ms_fwd = timed(lambda: [B.md_newton_step(sd, x, nrm, ws_n, st, stream)
                             for _ in range(iters)], 1) / iters
     G = 2 * x
-    res = {}
-    grads = {}
+    res, grads = {}, {}
     for store in (True, False):
         fn = B.MD_FN_ADJOINT_STORE if store else B.MD_FN_ADJOINT
         ws = B.workspace(fn, m, n, n, d, sysm.M, sysm.max_deg)
@@ -265,7 +342,6 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
               f"multi-GPU path", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
     from paper_2012_06607_amd import binding as B
     from paper_2012_06607_amd import opcount as OC
@@ -274,104 +350,64 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     B.lib()
-    sysm, x_h, A_h, b_h = make_inputs()
-    dev = torch.device("cuda")
-    sd = B.DeviceSystem(sysm)
-    x = torch.as_tensor(x_h, device=dev)
-    A = torch.as_tensor(A_h, device=dev)
-    b = torch.as_tensor(b_h, device=dev)
-    A0 = A[:, :, 0].contiguous()
-    f = torch.empty((2, M, D + 1, N), dtype=torch.float64, device=dev)
-    Aev = torch.empty((2, M, D + 1, N, N), dtype=torch.float64, device=dev)
-    dx = torch.empty((2, M, D + 1, N), dtype=torch.float64, device=dev)
-    ws_eval = B.workspace(B.MD_FN_EVAL, M, N, N, D, sysm.M, sysm.max_deg, dev)
-    ws_solve = B.workspace(B.MD_FN_SOLVE, M, N, N, D, 0, 0, dev)
-    QRb = torch.empty_like(A0)
-    vdb = torch.empty((2, M, N), dtype=torch.float64, device=dev)
-    betab = torch.empty((M, N), dtype=torch.float64, device=dev)
-    status = torch.zeros(1, dtype=torch.int32, device=dev)
-    stream = torch.cuda.current_stream()
-
-    def step(ev=None):
-        if ev is not None:
-            ev[0].record(stream)
-        B.md_poly_eval_diff(sd, x, f, Aev, ws_eval, stream)
-        if ev is not None:
-            ev[1].record(stream)
-        QR, vd, beta, _ = B.md_qr(A0, status, stream, QRb, vdb, betab)
-        if ev is not None:
-            ev[2].record(stream)
-        B.md_series_solve(QR, vd, beta, A, b, dx, ws_solve, status, stream)
-        if ev is not None:
-            ev[3].record(stream)
-
+    paths = make_paths(args.paths)
     if args.copy_mib > 0:
-        src = torch.ones(args.copy_mib << 17, dtype=torch.float64, device=dev)
+        src = torch.ones(args.copy_mib << 17, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         torch.neg(src, out=dst)   # reads and writes copy_mib MiB each
         torch.cuda.synchronize()
         del src, dst
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    K = args.steps
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_start.record(stream)
-    for s in range(K):
-        step(evs[s])
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    total_ms = t_start.elapsed_time(t_end)
-    ms_per_step = total_ms / K
-    st = int(status.item())
-
-    names = ("md_poly_eval_diff", "md_qr", "md_series_solve")
-    dur = {nm: float(np.mean([evs[s][i].elapsed_time(evs[s][i + 1]) for s in range(K)]))
-           for i, nm in enumerate(names)}
-    ops = {"md_poly_eval_diff": OC.eval_diff(sysm, D).table_ops(M),
-           "md_qr": OC.qr(N, N, M).table_ops(M),
-           "md_series_solve": OC.series_solve(N, N, D).table_ops(M)}
-    step_ops = sum(ops.values())
-    # the dominant kernel is k_qr, md_qr's single launch (the solve is about
-    # 40 launches, the largest of them k_pinv_cols)
-    achieved = ops["md_qr"] / (dur["md_qr"] * 1e-3) / 1e12
+    r = batched(args, B, OC, paths)
+    ms = r["ms"]
+    steps_per_launch = len(paths) * ITERS
+    value = steps_per_launch / (ms * 1e-3)
+    achieved = r["ops"] / (ms * 1e-3) / 1e12
     peak = OC.FP64_VECTOR_PEAK / 1e12
-    value = 1000.0 / ms_per_step
     line = {
         "metric": METRIC,
-        "value": round(value, 3),
-        "unit": "steps/s",
+        "value": round(value, 2),
+        "unit": "Newton steps/s",
         "n_gpus": 1,
-        "steps": K,
+        "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": round(ms, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "precision": "quad double (m=4)", "n": N, "N": N, "d": D,
-                   "monomials_per_equation": 16, "max_degree": 4, "cond_A0": 1e3},
-        "pct_fp64_vector_peak": round(100.0 * step_ops * value / OC.FP64_VECTOR_PEAK, 3),
-        "table_ops_per_step": step_ops,
-        "kernels_ms": {k: round(v, 4) for k, v in dur.items()},
-        "roofline": {"kernel": "k_qr (md_qr)", "bound": "alu", "achieved": round(achieved, 5),
-                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 6),
-                     "traffic": qr_traffic_bytes(),
-                     "basis": "Table 1 hardware-double operations of the QR's multiple-double "
-                              "operations per launch / mean launch time (HIP events); traffic: "
-                              "HBM bytes per launch from FETCH_SIZE + WRITE_SIZE, copy-scaled"},
-        "status": st,
+        "config": {"workload": WORKLOAD, "paths": len(paths), "newton_steps_per_path": ITERS,
+                   "newton_steps_per_launch": steps_per_launch,
+                   "precisions": "double double (m=2) and quad double (m=4), 50/50",
+                   "launch": r["shape"]},
+        "pct_fp64_vector_peak": round(100.0 * achieved / peak, 3),
+        "table_ops_per_step": r["ops"],
+        "roofline": {"kernel": "k_newton_batch", "bound": "alu", "achieved": round(achieved, 4),
+                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 5),
+                     "traffic": traffic_bytes("k_newton_batch"),
+                     "basis": "Table 1 hardware-double operations of the md operations of "
+                              "every Newton step of the launch / mean launch time (HIP "
+                              "events on the launch stream); traffic: HBM bytes per launch "
+                              "from FETCH_SIZE + WRITE_SIZE, copy-scaled"},
+        "qd_share_of_ops": round(r["qd_share"], 4),
+        "status": r["status"],
     }
-    if not args.no_batched:
-        line["batched"] = batched_measure(args, B, OC)
+    if r.get("tuned"):
+        t = r["tuned"]
+        line["tuner"] = {"trials": len(t["trials"]), "best": t["best"],
+                         "slowest_path_ms": round(1e3 * t["path_seconds"]["max"], 3),
+                         "sum_path_ms": round(1e3 * t["path_seconds"]["sum"], 1)}
+    if "loop_ms" in r:
+        line["per_path_loop"] = {"ms": round(r["loop_ms"], 3),
+                                 "speedup_of_batched": round(r["loop_ms"] / ms, 2),
+                                 "max_diff_vs_batched_in_2^-(53m-8)_units":
+                                     round(r["diff_units"], 3)}
+    if not args.no_single:
+        line["single_path"] = single_path(args, B, OC)
     if not args.no_adjoint:
         line["adjoint"] = adjoint_measure(args, B, OC)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(sysm, x_h, A_h, b_h, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(paths, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 
 

@@ -83,9 +83,10 @@ __device__ __forceinline__ void newton_path(const md_path &p, int iters, const i
   a.f = f;
   a.A = A;
   const int seg = N >= WAVE ? WAVE : pow2_at_least(N);
-  const int seg_dx = dot_seg(N), seg_up = dot_seg(n);
-  const int spw = WAVE / seg, nslots = nwaves * spw;
-  const int slot = wave * spw + lane_id() / seg;
+  const int seg_dx = dot_seg_throughput(N), seg_up = dot_seg_throughput(n);
+  const int seg_p = pow2_at_least((N + 1) / 2);  // R^{-1} Q^H: two rows per lane
+  const int spw_p = WAVE / seg_p, nslots_p = nwaves * spw_p;
+  const int slot_p = wave * spw_p + lane_id() / seg_p;
   const int spw_x = WAVE / seg_dx, nslots_x = nwaves * spw_x;
   const int slot_x = wave * spw_x + lane_id() / seg_dx;
   const int spw_u = WAVE / seg_up, nslots_u = nwaves * spw_u;
@@ -101,16 +102,16 @@ __device__ __forceinline__ void newton_path(const md_path &p, int iters, const i
       for (int tau = wave; tau < p.M; tau += eval_waves)
         eval_term_wave<M>(a, tau, rgrp, lds + wave * per_wave, [] { wave_sync(); });
     __syncthreads();
-    for (long g = tid; g < long(L) * N * (n + 1); g += nt) eval_accumulate_elem<M>(a, g);
+    for (int g = tid; g < L * N; g += nt) eval_accumulate_row<M>(a, g % N, g / N);
     __syncthreads();
     for (long e = tid; e < Er; e += nt) cstore<M>(r, Er, e, c_neg<M>(cload<M>(f, Er, e)));
     // QR of A_0 (the k = 0 block of A), then W = R^{-1} (Q^H)_{0:n}
     qr_wg<M, 1>(qsh, N, n, seg, A, long(L) * N * n, QR, vd, beta, st);
     inv_diag_range<M>(tid, nt, N, n, QR, invd, st);
     __syncthreads();
-    for (int base = 0; base < N; base += nslots) {
-      const int c = base + slot;
-      pinv_column<M, 1>(c < N, c, N, n, seg, QR, vd, beta, invd, W);
+    for (int base = 0; base < N; base += nslots_p) {
+      const int c = base + slot_p;
+      pinv_column<M, 2>(c < N, c, N, n, seg_p, QR, vd, beta, invd, W);
     }
     __syncthreads();
     // staggered substitution

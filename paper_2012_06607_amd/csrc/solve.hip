@@ -118,8 +118,8 @@ int solve_enqueue(int m, int N, int n, int d, const double *QR, const double *vd
     double *invd = G + size_t(2) * Mm * n * N;
     int rc = pinv_enqueue(Mm, N, n, QR, vdiag, beta, invd, G, status, s);
     if (rc) return rc;
-    const int seg_dx = dot_seg(N);
-    const int seg_up = dot_seg(n);
+    const int seg_dx = dot_seg_latency(N);
+    const int seg_up = dot_seg_latency(n);
     for (int k = 0; k <= d; ++k) {
       {
         const long waves = (long(n) * seg_dx + WAVE - 1) / WAVE;

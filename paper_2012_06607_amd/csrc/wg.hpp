@@ -327,12 +327,17 @@ __device__ __forceinline__ void pinv_column(bool live, int c, int N, int n, int 
   }
 }
 
-// Lanes per dot product of the staggered stages (length len): each lane sums
-// up to four products in sequence, then a segment tree adds the lanes.  The
-// choice depends on the length only, so the single-path kernels and the
-// batched kernel sum in the same order.
-__host__ __device__ inline int dot_seg(int len) {
-  const int s = pow2_at_least((len + 3) / 4);
+// Lanes per dot product of the staggered stages (length len).  The
+// single-path kernels take one product per lane (shortest chain); the
+// batched kernel, where a workgroup has many rows to do, lets each lane sum
+// up to eight products in sequence before the segment tree (fewest
+// instructions per row).  Each choice fixes the order of the sums.
+__host__ __device__ inline int dot_seg_latency(int len) {
+  const int s = pow2_at_least(len);
+  return s > WAVE ? WAVE : s;
+}
+__host__ __device__ inline int dot_seg_throughput(int len) {
+  const int s = pow2_at_least((len + 7) / 8);
   return s > WAVE ? WAVE : s;
 }
 
@@ -416,9 +421,22 @@ __host__ __device__ inline int term_lds_series(int Dmax) {
 // ceil((d+1)/2) * r <= 64
 __host__ __device__ inline int eval_group(int d) {
   const int P = (d + 2) / 2;
-  int r = 1;
-  while (P * r * 2 <= 64) r *= 2;
-  return r;
+  const int r = WAVE / P;
+  return r < 1 ? 1 : r;
+}
+
+// Sum over the r lanes of a group (r need not be a power of two; sub is the
+// lane's index in its group): s_sub += s_{sub+o} for o = p/2, ..., 1 with p
+// the power of two at least r, where sub < o and sub + o < r.  The group's
+// first lane holds the sum; the order is fixed.  For a power of two r this
+// is seg_reduce_c's order.
+template <int M>
+__device__ __forceinline__ mdc<M> group_reduce_c(mdc<M> s, int r, int sub) {
+  for (int o = pow2_at_least(r) >> 1; o > 0; o >>= 1) {
+    const mdc<M> t = shfl_down_c<M>(s, o);
+    if (sub < o && sub + o < r) s = c_add<M>(s, t);
+  }
+  return s;
 }
 
 template <int M>
@@ -444,18 +462,18 @@ __device__ __noinline__ void conv_group(const mdc<M> *X, int dx, const mdc<M> *Y
                                            int d, int r, double *ws, long Ews, long wbase,
                                            int mult) {
   const int lane = lane_id();
-  const int sub = lane & (r - 1);
   const int pg = lane / r;
+  const int sub = lane - pg * r;
   const int npg = WAVE / r;
   const int P = (d + 2) / 2;
   for (int base = 0; base < P; base += npg) {
     const int p = base + pg;
-    const bool live = p < P;
+    const bool live = p < P && pg < npg;
 #pragma unroll 1
     for (int q = 0; q < 2; ++q) {
       const int k = live ? (q == 0 ? p : d - p) : 0;
       mdc<M> z = live ? conv_part<M>(X, dx, Y, k, sub, r) : c_zero<M>();
-      z = seg_reduce_c<M>(z, r);
+      z = group_reduce_c<M>(z, r, sub);
       if (live && sub == 0 && (q == 0 || k != p)) {
         if (mult > 1) {
           z.re = md_muld<M>(z.re, double(mult));
@@ -537,8 +555,10 @@ __device__ __forceinline__ void eval_term_wave(const EvalArgs &a, int tau, int r
   }
 }
 
-// f_i[k] (l == n) or A_{i,l}[k]: the term slots of equation i added in term
-// order, from zero
+// f_i[k] (g's l == n) or A_{i,l}[k], one element per call (g over
+// (k, i, l)): the term slots of equation i that touch it, added in term
+// order from zero.  The same sums as eval_accumulate_row, spread over more
+// threads for the single-path kernel.
 template <int M>
 __device__ __forceinline__ void eval_accumulate_elem(const EvalArgs &a, long g) {
   const int L = a.d + 1;
@@ -565,6 +585,34 @@ __device__ __forceinline__ void eval_accumulate_elem(const EvalArgs &a, long g) 
   }
   if (l == a.n) cstore<M>(a.f, long(L) * a.N, long(k) * a.N + i, acc);
   else cstore<M>(a.A, long(L) * a.N * a.n, (long(k) * a.N + i) * a.n + l, acc);
+}
+
+// Coefficient k of f_i and of row i of A: zero, then the terms of equation
+// i added in term order, the value slot into f_i and, for every distinct
+// factor l of a term, its derivative slot (first occurrence of l) into
+// A_{i,l}.  Each sum starts from zero and adds in term order, as the
+// definition reads; entries no term touches stay zero.
+template <int M>
+__device__ __forceinline__ void eval_accumulate_row(const EvalArgs &a, int i, int k) {
+  const int L = a.d + 1;
+  const long EA = long(L) * a.N * a.n;
+  const long rowA = (long(k) * a.N + i) * a.n;
+  for (int l = 0; l < a.n; ++l) cstore<M>(a.A, EA, rowA + l, c_zero<M>());
+  mdc<M> acc = c_zero<M>();
+  for (int tau = a.eq_ptr[i]; tau < a.eq_ptr[i + 1]; ++tau) {
+    const long wb = long(tau) * a.S * L + k;
+    acc = c_add<M>(acc, cload<M>(a.ws, a.Ews, wb + long(a.lay.val()) * L));
+    const int b = a.term_ptr[tau], e = a.term_ptr[tau + 1];
+    if (e - b > a.Dmax) continue;
+    for (int q = b; q < e; ++q) {
+      if (q > b && a.factors[q] == a.factors[q - 1]) continue;
+      const long el = rowA + a.factors[q];
+      cstore<M>(a.A, EA, el,
+                c_add<M>(cload<M>(a.A, EA, el),
+                         cload<M>(a.ws, a.Ews, wb + long(a.lay.der(q - b + 1)) * L)));
+    }
+  }
+  cstore<M>(a.f, long(L) * a.N, long(k) * a.N + i, acc);
 }
 
 // ---------------------------------------------------------------------------
