@@ -394,7 +394,7 @@ def main():
     }
     if r.get("tuned"):
         t = r["tuned"]
-        line["tuner"] = {"trials": len(t["trials"]), "best": t["best"],
+        line["tuner"] = {"trials": len(t["trials"]), "best": t["best"], "gangs": t["gangs"],
                          "slowest_path_ms": round(1e3 * t["path_seconds"]["max"], 3),
                          "sum_path_ms": round(1e3 * t["path_seconds"]["sum"], 1)}
     if "loop_ms" in r:

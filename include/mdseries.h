@@ -59,7 +59,9 @@ enum {
 enum {
   MD_ST_SINGULAR = 1,  /* a Householder column or a diagonal of R is zero */
   MD_ST_NONFINITE = 2, /* an infinity or NaN reached a result */
-  MD_ST_BADPATH = 4    /* md_newton_batch: a path's sizes or precision are not supported */
+  MD_ST_BADPATH = 4,   /* md_newton_batch: a path's sizes or precision are not supported */
+  MD_ST_GANG = 8,      /* md_newton_batch: a gang barrier waited too long (results invalid) */
+  MD_ST_NOTRUN = 16    /* md_newton_batch: no workgroup took the path's jobs */
 };
 
 /* Polynomial system f = (f_1..f_N) in x = (x_1..x_n), N >= n, whose terms
@@ -227,24 +229,39 @@ typedef struct md_path {
 /* LDS bytes the batched kernel needs for its evaluation stage. */
 size_t md_batch_lds_bytes(int max_m, int max_d, int max_deg, int eval_waves);
 
-/* Runs `iters` Newton steps on each of `npaths` paths.  paths: device
- * md_path[npaths]; order: device int32[npaths], the order in which jobs are
- * handed out (a permutation of 0..npaths-1); counter: a device int32 used as
- * the job counter (reset by the call itself, on the stream, so the call can
- * be captured in a graph and replayed); status: device int32[npaths],
- * MD_ST_* bits per path, cleared by the caller; max_m, max_d, max_deg:
- * maxima over the paths (host values, they size the LDS); grid: the number
- * of persistent workgroups; block: threads per workgroup, 256 or 512;
- * eval_waves (1..block/64): waves per workgroup that evaluate terms;
- * path_clock (may be NULL): device int64[2*npaths], receives for every path
- * the device wall clock (md_wall_clock_hz ticks per second) when its
- * workgroup took it and when it finished (for schedule tuning).
+/* Runs `iters` Newton steps on each of `npaths` paths in one persistent
+ * launch.  paths: device md_path[npaths].  Jobs: device int32[2*njobs],
+ * job j = (path, (G << 8) | member): a path is run by G workgroups (a gang,
+ * 1 <= G <= 32, members 0..G-1, one job each, consecutive in one queue).
+ * nq queues: queue q holds jobs qbegin[q]..qbegin[q+1]-1 (device
+ * int32[nq+1]) and is served, in order, by the workgroups running on
+ * accelerator die q (md_device_dies); with nq == 1 every workgroup serves
+ * the one queue.  Every queue needs at least as many resident workgroups
+ * as its largest gang.  counters: device int32[nq],
+ * gang_ctr: device int32[npaths], both scratch that the call resets on the
+ * stream (so the call can be captured in a graph and replayed).  status:
+ * device int32[npaths], MD_ST_* bits per path (cleared by the caller; the
+ * call sets MD_ST_NOTRUN first and clears it when the path is done).
+ * max_m, max_d, max_deg: maxima over the paths (host values, they size the
+ * LDS); grid: the number of persistent workgroups (each queue needs as many
+ * resident workgroups on its die as its largest gang); block: threads per
+ * workgroup, 256 or 512; eval_waves (1..block/64): waves per workgroup that
+ * evaluate terms; path_clock (may be NULL): device int64[2*npaths],
+ * receives for every path the device wall clock (md_wall_clock_hz ticks per
+ * second) when its member 0 took it and when it finished.
  * Errors: MD_EINVAL, MD_ENULL, MD_ESHAPE (LDS above md_device_lds_bytes()),
  * MD_EHIP. */
-int md_newton_batch(int npaths, const md_path *paths, const int32_t *order, const int32_t *ints,
-                    double *reals, double *ws, int iters, int32_t *counter, int32_t *status,
-                    int max_m, int max_d, int max_deg, int grid, int block, int eval_waves,
+int md_newton_batch(int npaths, const md_path *paths, int njobs, const int32_t *jobs, int nq,
+                    const int32_t *qbegin, const int32_t *ints, double *reals, double *ws,
+                    int iters, int32_t *counters, int32_t *gang_ctr, int32_t *status, int max_m,
+                    int max_d, int max_deg, int grid, int block, int eval_waves,
                     int64_t *path_clock, void *stream);
+
+/* Writes, for each of nblocks workgroups of a small launch, the accelerator
+ * die (XCC) it ran on: device int32[nblocks].  The queues of
+ * md_newton_batch are indexed by these ids.  Errors: MD_ENULL, MD_EINVAL,
+ * MD_EHIP. */
+int md_device_dies(int32_t *ids, int nblocks, void *stream);
 
 /* Largest dynamic LDS in bytes that the kernels may take on the current
  * device (the per-workgroup limit less 4 KiB for static LDS); bounds

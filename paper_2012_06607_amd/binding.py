@@ -385,11 +385,11 @@ class BatchedPaths:
         ws = torch.empty(n_ws + 32, dtype=torch.float64, device=dev)
         off = ((-ws.data_ptr()) % 256) // 8
         self.ws = ws[off:off + max(n_ws, 1)]
-        if order is None:
-            order = np.argsort(-cost, kind="stable")
-        self.order = torch.as_tensor(np.asarray(order, dtype=np.int32), device=dev)
-        self.counter = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.device = dev
+        self.counters = torch.zeros(64, dtype=torch.int32, device=dev)
+        self.gang_ctr = torch.zeros(max(len(paths), 1), dtype=torch.int32, device=dev)
         self.status = torch.zeros(max(len(paths), 1), dtype=torch.int32, device=dev)
+        self.set_schedule(order=order)
 
     def x(self, p: int) -> torch.Tensor:
         m, N, n, d = self.meta[p]
@@ -408,11 +408,55 @@ class BatchedPaths:
         self.status.zero_()
 
     def set_order(self, order):
-        """Job order (a permutation of the paths)."""
-        order = np.asarray(order, dtype=np.int32)
-        if sorted(order.tolist()) != list(range(self.npaths)):
-            raise MdError("order must be a permutation of the paths")
-        self.order = torch.as_tensor(order, device=self.order.device)
+        """One queue, one workgroup per path, jobs in the given order (a
+        permutation of the paths)."""
+        self.set_schedule(order=order)
+
+    def set_schedule(self, order=None, gangs=None, nq: int = 1, weights=None):
+        """Job lists for md_newton_batch.  order: job order for one queue
+        (default: longest first by the analytic cost).  nq > 1: the paths are
+        spread over nq queues (one per accelerator die), longest first onto
+        the least loaded queue by `weights` (default the analytic cost), and
+        each queue runs its paths longest first; gangs (G per path) split a
+        path over G workgroups (of one die when nq > 1)."""
+        npaths = self.npaths
+        w = np.asarray(self.cost if weights is None else weights, dtype=np.float64)
+        G = np.ones(npaths, dtype=np.int64) if gangs is None else np.asarray(gangs, dtype=np.int64)
+        if G.shape != (npaths,) or G.min(initial=1) < 1 or G.max(initial=1) > 32:
+            raise MdError("gangs must give 1..32 workgroups per path")
+        if nq < 1 or nq > 64:
+            raise MdError("nq must be in 1..64")
+        if order is not None:
+            order = np.asarray(order, dtype=np.int64)
+            if sorted(order.tolist()) != list(range(npaths)):
+                raise MdError("order must be a permutation of the paths")
+            if nq != 1:
+                raise MdError("an explicit order is for one queue")
+            queues = [order]
+        else:
+            by_w = np.argsort(-w, kind="stable")
+            if nq == 1:
+                queues = [by_w]
+            else:
+                load = np.zeros(nq)
+                qs = [[] for _ in range(nq)]
+                for p in by_w:
+                    q = int(np.argmin(load))
+                    qs[q].append(int(p))
+                    load[q] += w[p]
+                queues = [np.asarray(qp, dtype=np.int64) for qp in qs]
+        jobs, qbegin = [], [0]
+        for qp in queues:
+            for p in qp:
+                for r in range(int(G[p])):
+                    jobs.append((int(p), (int(G[p]) << 8) | r))
+            qbegin.append(len(jobs))
+        self.nq = nq
+        self.gangs = G
+        self.njobs = len(jobs)
+        self.jobs = torch.as_tensor(np.asarray(jobs, dtype=np.int32).reshape(-1) if jobs
+                                    else np.zeros(2, np.int32), device=self.device)
+        self.qbegin = torch.as_tensor(np.asarray(qbegin, dtype=np.int32), device=self.device)
 
     def reset(self, paths):
         """Put the start series back (same structure as at construction)."""
@@ -432,29 +476,53 @@ def md_newton_batch(batch: BatchedPaths, iters: int, grid: int | None = None,
                     eval_waves: int | None = None, stream=None, block: int = 256,
                     path_clock: torch.Tensor | None = None):
     """`iters` Newton steps on every path of the batch in one persistent
-    launch (the library resets the job counter on the stream first).
-    path_clock: optional int64 device tensor (npaths, 2) that receives each
-    path's start and end on the device wall clock."""
+    launch, with the batch's job schedule (BatchedPaths.set_schedule; the
+    library resets the counters on the stream first).  path_clock: optional
+    int64 device tensor (npaths, 2) that receives each path's start and end
+    on the device wall clock."""
     L = lib()
     P, i32 = ctypes.c_void_p, ctypes.c_int
-    L.md_newton_batch.argtypes = [i32, P, P, P, P, P, i32, P, P, i32, i32, i32, i32, i32, i32, P, P]
+    L.md_newton_batch.argtypes = [i32, P, i32, P, i32, P, P, P, P, i32, P, P, P, i32, i32, i32,
+                                  i32, i32, i32, P, P]
     L.md_newton_batch.restype = ctypes.c_int
     if eval_waves is None:
-        eval_waves = 4
+        eval_waves = block // 64
         while eval_waves > 1 and md_batch_lds_bytes(batch.max_m, batch.max_d, batch.max_deg,
                                                      eval_waves) > md_device_lds_bytes():
             eval_waves -= 1
     if grid is None:
         props = torch.cuda.get_device_properties(batch.reals.device)
-        grid = 2 * props.multi_processor_count
+        grid = props.multi_processor_count
     if path_clock is not None and tuple(path_clock.shape) != (batch.npaths, 2):
         raise MdError("path_clock must have shape (npaths, 2)")
-    _check(L.md_newton_batch(batch.npaths, _ptr(batch.paths_dev, torch.uint8), _ptr(batch.order, torch.int32),
-                             _ptr(batch.ints, torch.int32), _ptr(batch.reals), _ptr(batch.ws),
-                             iters, _ptr(batch.counter, torch.int32), _ptr(batch.status, torch.int32),
-                             batch.max_m, batch.max_d, batch.max_deg, grid, block, eval_waves,
+    if grid < batch.nq * int(batch.gangs.max(initial=1)):
+        raise MdError(f"grid={grid} too small for {batch.nq} queues with gangs of "
+                      f"{int(batch.gangs.max(initial=1))}")
+    _check(L.md_newton_batch(batch.npaths, _ptr(batch.paths_dev, torch.uint8), batch.njobs,
+                             _ptr(batch.jobs, torch.int32), batch.nq,
+                             _ptr(batch.qbegin, torch.int32), _ptr(batch.ints, torch.int32),
+                             _ptr(batch.reals), _ptr(batch.ws), iters,
+                             _ptr(batch.counters, torch.int32), _ptr(batch.gang_ctr, torch.int32),
+                             _ptr(batch.status, torch.int32), batch.max_m, batch.max_d,
+                             batch.max_deg, grid, block, eval_waves,
                              _ptr(path_clock, torch.int64), _stream(stream)), "md_newton_batch")
     return batch
+
+
+_dies = {}
+
+
+def md_device_dies(device: int = 0) -> int:
+    """Number of accelerator dies the queues of md_newton_batch map to
+    (distinct die ids over a small launch)."""
+    if device not in _dies:
+        L = lib()
+        L.md_device_dies.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
+        ids = torch.full((256,), -1, dtype=torch.int32, device=f"cuda:{device}")
+        _check(L.md_device_dies(_ptr(ids, torch.int32), 256, _stream(None)), "md_device_dies")
+        v = ids.cpu().numpy()
+        _dies[device] = int(v.max()) + 1
+    return _dies[device]
 
 
 def md_device_lds_bytes() -> int:

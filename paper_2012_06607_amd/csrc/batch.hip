@@ -4,14 +4,21 @@
 // the workers start, each job reads shared inputs and writes its own
 // workspace, and a counter guarded by a lock hands out the next job.  Here
 // the workers are workgroups resident on the GPU, the counter is one device
-// atomic, and a job is a whole path: `iters` Newton steps (evaluation and
-// differentiation, QR of A_0, R^{-1} Q^H, the staggered solve, the update)
-// run by that workgroup with barriers between the stages (the paper's stage
-// synchronisation by terminating tasks).  Paths are taken in the order the
-// caller gives (longest first balances the load), and each workgroup
-// dispatches on its path's precision.  Every stage runs the same
-// segment-level code as the single-path entry points, so a batched path
-// gives the same bits as md_newton_step on that path.
+// atomic per queue, and a job is a whole path: `iters` Newton steps
+// (evaluation and differentiation, QR of A_0, R^{-1} Q^H, the staggered
+// solve, the update) run by that workgroup with barriers between the stages
+// (the paper's stage synchronisation by terminating tasks).  Jobs are taken
+// in the order the caller gives (longest first balances the load), and each
+// workgroup dispatches on its path's precision.
+//
+// A large path may be a gang of G workgroups (G members, one job each).
+// The members split the term evaluations, the Jacobian rows, the columns of
+// R^{-1} Q^H and the right-hand-side updates, and meet at gang barriers (a
+// counter in device memory, with device-scope release and acquire).  The QR
+// and the update of x run on member 0; every member computes the stage
+// products dx_k itself (the same bits), so a stage costs one gang barrier.
+// With one queue per accelerator die (queue q served by the workgroups on
+// die q) a gang's members share that die's L2.
 #include "internal.hpp"
 #include "wg.hpp"
 
@@ -41,11 +48,46 @@ __device__ mdr<M> wg_max(mdr<M> v, mdr<M> *sh) {
   return v;
 }
 
+// Accelerator die (XCC) of the calling wave.
+__device__ __forceinline__ int xcc_id() {
+  unsigned v;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+  return int(v & 0xf);
+}
+
+// Gang barrier: every thread's memory operations complete, then member
+// thread 0 releases at device scope (the workgroup's stores become visible
+// to the other members), arrives on the counter and waits for all G
+// arrivals of this round (bounded: a round that never completes sets
+// MD_ST_GANG, and after that the workgroup waits no more), then acquires at
+// device scope (stale cache lines dropped) before the workgroup goes on.
+__device__ __forceinline__ void gang_barrier(int32_t *ctr, int G, int &round, int &st) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int target = (round + 1) * G;
+    long spins = (st & MD_ST_GANG) ? (1L << 25) : 0;
+    // polled with an atomic (performed where the arrivals are performed)
+    while (__hip_atomic_fetch_add(ctr, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins >= (1L << 25)) {
+        st |= MD_ST_GANG;
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+  ++round;
+}
+
 template <int M>
 __device__ __forceinline__ void newton_path(const md_path &p, int iters, const int32_t *__restrict__ ints,
                             double *__restrict__ reals, double *__restrict__ wsb,
                             int32_t *__restrict__ status, int path, double *lds_raw,
-                            int eval_waves) {
+                            int eval_waves, int member, int G, int32_t *gang_ctr) {
   __shared__ QrShared<M> qsh;
   __shared__ mdr<M> msh[16];  // one per wave, up to 1024 threads
   const int N = p.N, n = p.n, d = p.d, L = d + 1;
@@ -95,26 +137,39 @@ __device__ __forceinline__ void newton_path(const md_path &p, int iters, const i
   const int per_wave = term_lds_series(p.max_deg) * L;
   mdc<M> *lds = reinterpret_cast<mdc<M> *>(lds_raw);
   const long Ex = long(L) * n, Er = long(L) * N;
-  int st = 0;
+  int st = 0, round = 0;
+  auto gsync = [&] {
+    if (G > 1) gang_barrier(gang_ctr, G, round, st);
+    else __syncthreads();
+  };
   for (int it = 0; it < iters; ++it) {
-    // evaluation and differentiation: waves over terms, then the sums
+    // evaluation and differentiation: waves (of all members) over terms,
+    // then the sums, one (equation, coefficient) pair per thread, with
+    // r = -f written by the thread that formed f
     if (wave < eval_waves)
-      for (int tau = wave; tau < p.M; tau += eval_waves)
+      for (int tau = member * eval_waves + wave; tau < p.M; tau += G * eval_waves)
         eval_term_wave<M>(a, tau, rgrp, lds + wave * per_wave, [] { wave_sync(); });
-    __syncthreads();
-    for (int g = tid; g < L * N; g += nt) eval_accumulate_row<M>(a, g % N, g / N);
-    __syncthreads();
-    for (long e = tid; e < Er; e += nt) cstore<M>(r, Er, e, c_neg<M>(cload<M>(f, Er, e)));
-    // QR of A_0 (the k = 0 block of A), then W = R^{-1} (Q^H)_{0:n}
-    qr_wg<M, 1>(qsh, N, n, seg, A, long(L) * N * n, QR, vd, beta, st);
-    inv_diag_range<M>(tid, nt, N, n, QR, invd, st);
-    __syncthreads();
-    for (int base = 0; base < N; base += nslots_p) {
+    gsync();
+    for (int g = member * nt + tid; g < L * N; g += G * nt) {
+      const int i = g % N, k = g / N;
+      eval_accumulate_row<M>(a, i, k);
+      cstore<M>(r, Er, long(k) * N + i, c_neg<M>(cload<M>(f, Er, long(k) * N + i)));
+    }
+    gsync();
+    // QR of A_0 (the k = 0 block of A) on member 0, then W = R^{-1}
+    // (Q^H)_{0:n}, columns over all members
+    if (member == 0) {
+      qr_wg<M, 1>(qsh, N, n, seg, A, long(L) * N * n, QR, vd, beta, st);
+      inv_diag_range<M>(tid, nt, N, n, QR, invd, st);
+    }
+    gsync();
+    for (int base = member * nslots_p; base < N; base += G * nslots_p) {
       const int c = base + slot_p;
       pinv_column<M, 2>(c < N, c, N, n, seg_p, QR, vd, beta, invd, W);
     }
-    __syncthreads();
-    // staggered substitution
+    gsync();
+    // staggered substitution: every member forms dx_k, the updates of the
+    // later right hand sides are split over the members
     for (int k = 0; k <= d; ++k) {
       for (int base = 0; base < n; base += nslots_x) {
         const int i = base + slot_x;
@@ -123,14 +178,18 @@ __device__ __forceinline__ void newton_path(const md_path &p, int iters, const i
       __syncthreads();
       if (k < d) {
         const long rows = long(d - k) * N;
-        for (long base = 0; base < rows; base += nslots_u) {
+        for (long base = long(member) * nslots_u; base < rows; base += long(G) * nslots_u) {
           const long row = base + slot_u;
           stage_update_row<M>(row < rows, row, k, N, n, d, seg_up, A, dx, r);
         }
-        __syncthreads();
+        gsync();
       }
     }
-    // x += dx and the size of the update
+    if (member != 0) {
+      if (it + 1 < iters) gsync();
+      continue;
+    }
+    // x += dx and the size of the update (member 0)
     mdr<M> bd = md_zero<M>(), ba = md_zero<M>();
     for (long e = tid; e < Ex; e += nt) {
       const mdc<M> u = cload<M>(dx, Ex, e);
@@ -145,48 +204,73 @@ __device__ __forceinline__ void newton_path(const md_path &p, int iters, const i
       rstore<M>(reals + p.dx_norm, 2, 0, md_sqrt<M>(bd));
       rstore<M>(reals + p.dx_norm, 2, 1, md_sqrt<M>(ba));
     }
-    __syncthreads();
+    if (it + 1 < iters) gsync();
+    else __syncthreads();
   }
-  if (st) atomicOr(status + path, st);
+  if (tid == 0) {
+    if (st) atomicOr(status + path, st);
+    if (member == 0) atomicAnd(status + path, ~MD_ST_NOTRUN);
+  }
 }
 
-__global__ void k_reset_counter(int32_t *counter) { atomicExch(counter, 0); }
+// Before a launch: the job counters and the gang counters to zero, and every
+// path marked not run (its member 0 clears the mark when it is done).
+__global__ void __launch_bounds__(256) k_reset(int nq, int32_t *counters, int npaths,
+                                               int32_t *gang_ctr, int32_t *status) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nq) counters[t] = 0;
+  if (t < npaths) {
+    gang_ctr[t] = 0;
+    atomicOr(status + t, MD_ST_NOTRUN);
+  }
+}
 
 template <int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_newton_batch(int npaths, const md_path *__restrict__ paths,
-                                                        const int32_t *__restrict__ order,
+                                                        const int32_t *__restrict__ jobs, int nq,
+                                                        const int32_t *__restrict__ qbegin,
                                                         const int32_t *__restrict__ ints,
                                                         double *__restrict__ reals,
                                                         double *__restrict__ wsb, int iters,
-                                                        int32_t *counter, int32_t *status,
-                                                        int eval_waves, int64_t *clk) {
+                                                        int32_t *counters, int32_t *gang_ctr,
+                                                        int32_t *status, int eval_waves,
+                                                        int64_t *clk) {
   extern __shared__ double lds_raw[];
   __shared__ int sh_job;
+  const int q = nq == 1 ? 0 : xcc_id() % nq;
+  const int begin = qbegin[q], end = qbegin[q + 1];
   while (true) {
-    if (threadIdx.x == 0) sh_job = atomicAdd(counter, 1);
+    if (threadIdx.x == 0) sh_job = begin + atomicAdd(counters + q, 1);
     __syncthreads();
     const int job = sh_job;
     __syncthreads();
-    if (job >= npaths) break;
-    const int path = order[job];
+    if (job >= end) break;
+    const int path = jobs[2 * job];
+    const int G = jobs[2 * job + 1] >> 8, member = jobs[2 * job + 1] & 0xff;
     const md_path p = paths[path];
-    const bool ok = p.N >= p.n && p.n >= 1 && p.N <= WAVE && p.d >= 0 && p.max_deg >= 0;
+    const bool ok = path >= 0 && path < npaths && G >= 1 && member < G && p.N >= p.n &&
+                    p.n >= 1 && p.N <= WAVE && p.d >= 0 && p.max_deg >= 0;
     if (!ok) {
-      if (threadIdx.x == 0) atomicOr(status + path, MD_ST_BADPATH);
+      if (threadIdx.x == 0 && path >= 0 && path < npaths) atomicOr(status + path, MD_ST_BADPATH);
       continue;
     }
-    if (clk && threadIdx.x == 0) clk[2 * path] = wall_clock64();
+    if (clk && threadIdx.x == 0 && member == 0) clk[2 * path] = wall_clock64();
+    int32_t *gc = gang_ctr + path;
     switch (p.m) {
-      case 1: newton_path<1>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves); break;
-      case 2: newton_path<2>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves); break;
-      case 3: newton_path<3>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves); break;
-      case 4: newton_path<4>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves); break;
+      case 1: newton_path<1>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc); break;
+      case 2: newton_path<2>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc); break;
+      case 3: newton_path<3>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc); break;
+      case 4: newton_path<4>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc); break;
       default:
         if (threadIdx.x == 0) atomicOr(status + path, MD_ST_BADPATH);
         break;
     }
-    if (clk && threadIdx.x == 0) clk[2 * path + 1] = wall_clock64();
+    if (clk && threadIdx.x == 0 && member == 0) clk[2 * path + 1] = wall_clock64();
   }
+}
+
+__global__ void k_xcc_ids(int32_t *out) {
+  if (threadIdx.x == 0) out[blockIdx.x] = xcc_id();
 }
 
 }  // namespace mds
@@ -199,17 +283,18 @@ extern "C" size_t md_batch_lds_bytes(int max_m, int max_d, int max_deg, int eval
          eval_waves;
 }
 
-extern "C" int md_newton_batch(int npaths, const md_path *paths, const int32_t *order,
-                               const int32_t *ints, double *reals, double *ws, int iters,
-                               int32_t *counter, int32_t *status, int max_m, int max_d,
-                               int max_deg, int grid, int block, int eval_waves,
-                               int64_t *path_clock, void *stream) {
-  if (npaths < 0 || iters < 0 || grid < 1 || (block != 256 && block != 512) || eval_waves < 1 ||
-      eval_waves > block / WAVE)
-    return fail(MD_EINVAL, "md_newton_batch: npaths=%d iters=%d grid=%d block=%d eval_waves=%d",
-                npaths, iters, grid, block, eval_waves);
+extern "C" int md_newton_batch(int npaths, const md_path *paths, int njobs, const int32_t *jobs,
+                               int nq, const int32_t *qbegin, const int32_t *ints, double *reals,
+                               double *ws, int iters, int32_t *counters, int32_t *gang_ctr,
+                               int32_t *status, int max_m, int max_d, int max_deg, int grid,
+                               int block, int eval_waves, int64_t *path_clock, void *stream) {
+  if (npaths < 0 || njobs < 0 || iters < 0 || grid < 1 || (block != 256 && block != 512) ||
+      eval_waves < 1 || eval_waves > block / WAVE || nq < 1 || nq > 64)
+    return fail(MD_EINVAL,
+                "md_newton_batch: npaths=%d njobs=%d iters=%d grid=%d block=%d eval_waves=%d nq=%d",
+                npaths, njobs, iters, grid, block, eval_waves, nq);
   if (npaths == 0) return MD_OK;
-  if (!paths || !order || !ints || !reals || !ws || !counter || !status)
+  if (!paths || !jobs || !qbegin || !ints || !reals || !ws || !counters || !gang_ctr || !status)
     return fail(MD_ENULL, "md_newton_batch: null pointer");
   const size_t lds = md_batch_lds_bytes(max_m, max_d, max_deg, eval_waves);
   if (lds == 0) return fail(MD_EINVAL, "md_newton_batch: max_m=%d must be in 1..4", max_m);
@@ -217,16 +302,24 @@ extern "C" int md_newton_batch(int npaths, const md_path *paths, const int32_t *
     return fail(MD_ESHAPE, "md_newton_batch: %zu bytes of LDS for the evaluation exceed %zu", lds,
                 lds_limit());
   hipStream_t s = (hipStream_t)stream;
-  k_reset_counter<<<dim3(1), dim3(1), 0, s>>>(counter);
+  const int nr = npaths > nq ? npaths : nq;
+  k_reset<<<dim3((nr + 255) / 256), dim3(256), 0, s>>>(nq, counters, npaths, gang_ctr, status);
   if (block == 256)
-    k_newton_batch<256><<<dim3(grid), dim3(256), lds, s>>>(npaths, paths, order, ints, reals, ws,
-                                                           iters, counter, status, eval_waves,
-                                                           path_clock);
+    k_newton_batch<256><<<dim3(grid), dim3(256), lds, s>>>(npaths, paths, jobs, nq, qbegin, ints,
+                                                           reals, ws, iters, counters, gang_ctr,
+                                                           status, eval_waves, path_clock);
   else
-    k_newton_batch<512><<<dim3(grid), dim3(512), lds, s>>>(npaths, paths, order, ints, reals, ws,
-                                                           iters, counter, status, eval_waves,
-                                                           path_clock);
+    k_newton_batch<512><<<dim3(grid), dim3(512), lds, s>>>(npaths, paths, jobs, nq, qbegin, ints,
+                                                           reals, ws, iters, counters, gang_ctr,
+                                                           status, eval_waves, path_clock);
   return check_launch("md_newton_batch");
+}
+
+extern "C" int md_device_dies(int32_t *ids, int nblocks, void *stream) {
+  if (!ids) return fail(MD_ENULL, "md_device_dies: null pointer");
+  if (nblocks < 1) return fail(MD_EINVAL, "md_device_dies: nblocks=%d", nblocks);
+  k_xcc_ids<<<dim3(nblocks), dim3(64), 0, (hipStream_t)stream>>>(ids);
+  return check_launch("md_device_dies");
 }
 
 extern "C" int md_wall_clock_hz(int device, int64_t *hz) {

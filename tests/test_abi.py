@@ -113,21 +113,30 @@ def test_adjoint_host_checks(lib):
 def test_batch_host_checks(lib):
     P = ctypes.c_void_p
     i = ctypes.c_int
-    lib.md_newton_batch.argtypes = [i, P, P, P, P, P, i, P, P, i, i, i, i, i, i, P, P]
+    lib.md_newton_batch.argtypes = [i, P, i, P, i, P, P, P, P, i, P, P, P, i, i, i, i, i, i, P, P]
     lib.md_batch_lds_bytes.argtypes = [i] * 4
     lib.md_batch_lds_bytes.restype = ctypes.c_size_t
     fake = P(4096)
-    args = [fake] * 5
+
+    def call(npaths=4, njobs=4, nq=1, iters=1, max_m=4, max_d=8, max_deg=3, grid=16, block=256,
+             ew=4, paths=fake):
+        return lib.md_newton_batch(npaths, paths, njobs, fake, nq, fake, fake, fake, fake, iters,
+                                   fake, fake, fake, max_m, max_d, max_deg, grid, block, ew, None,
+                                   None)
     # penta double paths are not carried by the batched kernel: rejected on the host
-    assert lib.md_newton_batch(4, *args, 1, fake, fake, 5, 8, 3, 16, 256, 4, None, None) == 1
-    assert lib.md_newton_batch(4, *args, 1, fake, fake, 4, 8, 3, 0, 256, 4, None, None) == 1   # grid 0
-    assert lib.md_newton_batch(4, *args, 1, fake, fake, 4, 8, 3, 16, 256, 5, None, None) == 1  # eval waves
-    assert lib.md_newton_batch(4, *args, 1, fake, fake, 4, 8, 3, 16, 512, 9, None, None) == 1
-    assert lib.md_newton_batch(4, *args, 1, fake, fake, 4, 8, 3, 16, 384, 4, None, None) == 1  # block
-    assert lib.md_newton_batch(4, None, *args[1:], 1, fake, fake, 4, 8, 3, 16, 256, 4, None,
-                               None) == 3
-    assert lib.md_newton_batch(0, *args, 1, fake, fake, 4, 8, 3, 16, 256, 4, None, None) == 0
-    # evaluation LDS above 64 KiB is refused (deca-size series on 4 waves)
+    assert call(max_m=5) == 1
+    assert call(grid=0) == 1
+    assert call(ew=5) == 1                      # more evaluation waves than the block has
+    assert call(block=512, ew=9) == 1
+    assert call(block=384) == 1
+    assert call(nq=0) == 1
+    assert call(njobs=-1) == 1
+    assert call(paths=None) == 3
+    assert call(npaths=0) == 0                  # empty batch
+    # evaluation LDS above the device limit is refused (deca-size series on 4 waves)
     assert lib.md_batch_lds_bytes(4, 200, 4, 4) > 64 * 1024
-    assert lib.md_newton_batch(4, *args, 1, fake, fake, 4, 200, 4, 16, 256, 4, None, None) == 2
+    assert call(max_d=200, max_deg=4) == 2
     assert lib.md_batch_lds_bytes(5, 8, 3, 4) == 0
+    lib.md_device_dies.argtypes = [P, i, P]
+    assert lib.md_device_dies(None, 4, None) == 3
+    assert lib.md_device_dies(fake, 0, None) == 1

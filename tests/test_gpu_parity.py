@@ -415,6 +415,33 @@ def test_batch_against_oracle_and_reruns(B):
             assert e[k] <= tol(m, math.log2(cond) + math.log2(k + 1) + 4), (p, k, e)
 
 
+def test_batch_gangs_and_die_queues(B):
+    """One queue per accelerator die, and the longest paths split over gangs
+    of 2 and 4 workgroups (of one die, or of any die with one queue), give
+    the bits of the one-queue launch."""
+    paths = small_batch(count=14, seed=3)
+    batch = B.BatchedPaths(paths)
+    B.md_newton_batch(batch, 2, block=512)
+    torch.cuda.synchronize()
+    ref = [host(batch.x(p)).copy() for p in range(len(paths))]
+    assert not host(batch.status).any()
+    dies = B.md_device_dies()
+    gangs = np.ones(len(paths), dtype=np.int64)
+    order = np.argsort(-batch.cost)
+    gangs[order[:2]] = 4
+    gangs[order[2:5]] = 2
+    for nq, g in ((dies, None), (dies, gangs), (1, gangs)):
+        batch.set_schedule(nq=nq, gangs=g)
+        batch.restore()
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        print(f"batch gangs nq={nq} gangs={None if g is None else g.tolist()}", flush=True)
+        B.md_newton_batch(batch, 2, block=512, grid=cus)
+        torch.cuda.synchronize()
+        assert not host(batch.status).any(), host(batch.status)
+        for p in range(len(paths)):
+            assert np.array_equal(host(batch.x(p)), ref[p]), (nq, p)
+
+
 @pytest.mark.skip(reason="stalled on the GPU box twice without a cause found in the code yet; "
                          "kept off the GPU until one is shown")
 def test_batch_flags_paths_above_64_unknowns(B):
