@@ -43,13 +43,14 @@ M1, N1, D1 = 4, 32, 16    # the single-path step
 # (--copy-mib 256).  Valid only for the kernel sources the counters were
 # taken on: dropped (null) when their hash differs.
 TRAFFIC = {
-    "k_newton_batch": {"fetch_kib": None, "fetch_scale": None, "write_kib": None,
-                       "write_scale": None, "sha256": "",
+    "k_newton_batch": {"fetch_kib": 71990867.4, "fetch_scale": 262144 / 131087.5,
+                       "write_kib": 43745624.5, "write_scale": 262144 / 262144.0,
+                       "sha256": "4494ce844b4529490648e72a177eff2fb95982382900960820bcec439ec4995a",
                        "sources": ("batch.hip", "internal.hpp", "common.hpp", "md.hpp", "wg.hpp",
                                    "layout.hpp", "series.hpp")},
-    "k_qr": {"fetch_kib": 134.6, "fetch_scale": 262144 / 131088.2, "write_kib": 67.0,
-             "write_scale": 262144 / 262146.8,
-             "sha256": "bb15957c50d71f61492f439d6df4a31e341a42d7dcb59a18a121cf51a64081f9",
+    "k_qr": {"fetch_kib": 134.625, "fetch_scale": 262144 / 131087.5, "write_kib": 67.0,
+             "write_scale": 262144 / 262144.0,
+             "sha256": "e9e175fcf10c91c5f03d3ba54110d843ed0ecd3aaa9ba41d91ac367d68edb60b",
              "sources": ("qr.hip", "internal.hpp", "common.hpp", "md.hpp", "wg.hpp",
                          "layout.hpp", "series.hpp")},
 }
@@ -80,6 +81,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the launch-shape tuner (512 threads, one workgroup per CU)")
+    ap.add_argument("--gang-factor", type=float, default=None,
+                    help="skip the tuner's trials: one queue per die, gangs for paths longer "
+                         "than this factor times the mean load per CU (durations measured in "
+                         "one run), 512 threads, one workgroup per CU")
     ap.add_argument("--no-loop", action="store_true", help="skip the per-path launch loop")
     ap.add_argument("--no-single", action="store_true",
                     help="skip the single-path step (32 unknowns, d = 16, quad double)")
@@ -136,12 +141,17 @@ def batched(args, B, OC, paths):
     ops = sum(ITERS * OC.newton_step(sysm, x.shape[2] - 1, sysm.m).table_ops(sysm.m)
               for sysm, x in paths)
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    if args.no_tune:
+    if args.no_tune or args.gang_factor is not None:
         shape = {"grid": cus, "block": 512, "eval_waves": 8}
         while shape["eval_waves"] > 1 and B.md_batch_lds_bytes(
                 batch.max_m, batch.max_d, batch.max_deg, shape["eval_waves"]) > B.md_device_lds_bytes():
             shape["eval_waves"] -= 1
         tuned = None
+        if args.gang_factor is not None:
+            from paper_2012_06607_amd.tune import gang_sizes, measured_durations
+            dur = measured_durations(batch, ITERS, stream, **shape)
+            batch.set_schedule(nq=B.md_device_dies(), weights=dur,
+                               gangs=gang_sizes(dur, cus, args.gang_factor))
     else:
         from paper_2012_06607_amd.tune import tune_batch
         tuned = tune_batch(batch, ITERS, stream=stream)
