@@ -455,13 +455,28 @@ __device__ __forceinline__ mdc<M> conv_part(const mdc<M> *X, int dx, const mdc<M
 
 // z = X Y (deg X <= dx) truncated at d for the coefficient pairs (k, d-k)
 // of this lane's group; the group's partial sums go through a fixed-order
-// tree; results (times `mult`) to LDS Z or to workspace planes.  Called by
-// all 64 lanes of a wave.
+// tree; results (times `mult`) to LDS Z or to workspace planes.  When X has
+// fewer coefficients than a group has lanes, each lane takes whole
+// coefficients instead.  Called by all 64 lanes of a wave.
 template <int M>
 __device__ __noinline__ void conv_group(const mdc<M> *X, int dx, const mdc<M> *Y, mdc<M> *Z,
                                            int d, int r, double *ws, long Ews, long wbase,
                                            int mult) {
   const int lane = lane_id();
+  if (dx < r) {
+    // a short X (a coefficient series): one coefficient per lane, its few
+    // products added in sequence
+    for (int k = lane; k <= d; k += WAVE) {
+      mdc<M> z = conv_part<M>(X, dx, Y, k, 0, 1);
+      if (mult > 1) {
+        z.re = md_muld<M>(z.re, double(mult));
+        z.im = md_muld<M>(z.im, double(mult));
+      }
+      if (Z) Z[k] = z;
+      else cstore<M>(ws, Ews, wbase + k, z);
+    }
+    return;
+  }
   const int pg = lane / r;
   const int sub = lane - pg * r;
   const int npg = WAVE / r;
