@@ -47,7 +47,7 @@ __global__ void __launch_bounds__(256) k_pinv_cols(int N, int n, int seg,
                                                    double *__restrict__ W) {
   const int gwave = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   const int c = gwave * (WAVE / seg) + lane_id() / seg;
-  pinv_column<M, RPL>(c < N, c, N, n, seg, QR, vdiag, beta, invd, W);
+  pinv_column<M, RPL, true>(c < N, c, N, n, seg, QR, vdiag, beta, invd, W);
 }
 
 // dx_k = W r_k: one segment per output row

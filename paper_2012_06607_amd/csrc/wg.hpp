@@ -79,10 +79,10 @@ struct QrShared {
   mdr<M> beta[2];
 };
 
-// Reflector j from the column values a segment holds (rows lis + r*seg): the
-// segment tree of |a_i|^2 over i >= j, alpha from the lane that holds row j;
-// lane 0 of the wave forms the scalars when `keep` (all lanes of the wave
-// call this; only the first segment's result is kept).
+// Reflector j from the column values the wave's first segment holds (rows
+// lis + r*seg): the segment tree of |a_i|^2 over i >= j, alpha from the lane
+// that holds row j; lane 0 of the wave stores the scalars when `keep` (all
+// lanes of the wave call this).
 template <int M, int RPL>
 __device__ __forceinline__ void qr_reflector(const mdc<M> (&col)[RPL], int j, int N, int n, int seg,
                                              bool keep, QrShared<M> &sh, double *__restrict__ QR,
@@ -104,27 +104,48 @@ __device__ __forceinline__ void qr_reflector(const mdc<M> (&col)[RPL], int j, in
     if (i == j) alpha = col[r];
   }
   s = seg_reduce_r<M>(s, seg);
-  alpha = shfl_c<M>(alpha, (lane & ~(seg - 1)) + (j & (seg - 1)));
-  if (keep && lane == 0) {
-    const mdr<M> s2 = s;
-    const mdr<M> a2 = c_abs2<M>(alpha);
-    const mdr<M> ys = rsqrt_doubling<M>(s2);
-    const mdr<M> ya = rsqrt_doubling<M>(a2);
-    const mdr<M> sigma = md_mul<M>(s2, ys);
-    mdr<M> aabs = md_mul<M>(a2, ya);
-    mdc<M> phi = c_zero<M>();
+  // The wave's first segment holds the column: its sums and alpha go to every
+  // lane, and the scalars are a short chain of md operations with the
+  // independent ones side by side on lanes 0..3 (lane 0 keeps the results):
+  // 1/sqrt and the product with it for sigma^2 (lane 0) and |alpha|^2
+  // (lane 1), then phi = alpha/|alpha| (re, im on lanes 0, 1), then v_0 =
+  // phi (|alpha| + sigma) and R_jj = -phi sigma (lanes 0..3).
+  alpha = shfl_c<M>(alpha, j & (seg - 1));
+  const int base = 0, sub = lane;
+  const mdr<M> s2 = shfl_r<M>(s, base);
+  const mdr<M> a2 = c_abs2<M>(alpha);
+  const mdr<M> xq = sub == 0 ? s2 : a2;
+  const mdr<M> yq = rsqrt_doubling<M>(xq);
+  const mdr<M> zq = md_mul<M>(xq, yq);
+  const mdr<M> ys = shfl_r<M>(yq, base), ya = shfl_r<M>(yq, base + 1);
+  const mdr<M> sigma = shfl_r<M>(zq, base);
+  const bool a_zero = a2.v[0] == 0.0;
+  const mdr<M> aabs = a_zero ? md_zero<M>() : shfl_r<M>(zq, base + 1);
+  const mdr<M> sp = md_add<M>(aabs, sigma);
+  const mdr<M> bet_q = md_div<M>(ys, sp);
+  const mdr<M> ph_q = md_mul<M>((sub & 1) ? alpha.im : alpha.re, ya);
+  mdc<M> phi;
+  if (a_zero) {
+    phi = c_zero<M>();
     phi.re = md_from<M>(1.0);
-    if (a2.v[0] != 0.0) phi = c_mulr<M>(alpha, ya);
-    else aabs = md_zero<M>();
+  } else {
+    phi.re = shfl_r<M>(ph_q, base);
+    phi.im = shfl_r<M>(ph_q, base + 1);
+  }
+  const mdr<M> w_q = md_mul<M>((sub & 1) ? phi.im : phi.re, (sub & 2) ? sigma : sp);
+  const mdr<M> w0 = shfl_r<M>(w_q, base), w1 = shfl_r<M>(w_q, base + 1);
+  const mdr<M> w2 = shfl_r<M>(w_q, base + 2), w3 = shfl_r<M>(w_q, base + 3);
+  if (keep && lane == 0) {
     mdr<M> bet = md_zero<M>();
     mdc<M> v0 = c_zero<M>(), rjj = c_zero<M>();
     if (s2.v[0] == 0.0) {
       st |= MD_ST_SINGULAR;
     } else {
-      const mdr<M> sp = md_add<M>(aabs, sigma);
-      v0 = c_mulr<M>(phi, sp);
-      bet = md_div<M>(ys, sp);
-      rjj = c_neg<M>(c_mulr<M>(phi, sigma));
+      v0.re = w0;
+      v0.im = w1;
+      bet = bet_q;
+      rjj.re = md_neg<M>(w2);
+      rjj.im = md_neg<M>(w3);
     }
     if (!c_finite<M>(rjj) || !md_finite<M>(bet)) st |= MD_ST_NONFINITE;
     sh.v0[j & 1] = v0;
@@ -262,7 +283,7 @@ __device__ __forceinline__ void inv_diag_range(int t, int nt, int N, int n, cons
 // lis, lis+seg, ...): identity column, n reflectors in order, then the back
 // substitution with the row owner multiplying by 1/R_ii and broadcasting.
 // W: row-major n x N.  `live` false: the segment only joins the shuffles.
-template <int M, int RPL>
+template <int M, int RPL, bool PF = false>
 __device__ __forceinline__ void pinv_column(bool live, int c, int N, int n, int seg,
                             const double *__restrict__ QR, const double *__restrict__ vdiag,
                             const double *__restrict__ beta, const double *__restrict__ invd,
@@ -277,18 +298,40 @@ __device__ __forceinline__ void pinv_column(bool live, int c, int N, int n, int 
     g[r] = c_zero<M>();
     if (live && lis + r * seg == c) g[r].re = md_from<M>(1.0);
   }
+  // reflector j's head, beta and this lane's rows of its tail; with PF the
+  // next reflector's are loaded while this one is applied
+  auto load_v = [&](int j, mdc<M> &v0, mdr<M> &bet, mdc<M> (&vi)[RPL]) {
+    v0 = cload<M>(vdiag, n, j);
+    bet = rload<M>(beta, n, j);
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int i = lis + r * seg;
+      vi[r] = c_zero<M>();
+      if (live && i > j && i < N) vi[r] = cload<M>(QR, E, long(i) * n + j);
+    }
+  };
+  mdc<M> v0n, vin[RPL];
+  mdr<M> betn;
+  if (PF && n > 0) load_v(0, v0n, betn, vin);
   for (int j = 0; j < n; ++j) {
-    const mdc<M> v0 = cload<M>(vdiag, n, j);
-    const mdr<M> bet = rload<M>(beta, n, j);
-    mdc<M> vi[RPL];
+    mdc<M> v0, vi[RPL];
+    mdr<M> bet;
+    if (PF) {
+      v0 = v0n;
+      bet = betn;
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) vi[r] = vin[r];
+      if (j + 1 < n) load_v(j + 1, v0n, betn, vin);
+    } else {
+      load_v(j, v0, bet, vi);
+    }
     mdc<M> w = c_zero<M>();
     bool first = true;
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
       const int i = lis + r * seg;
-      vi[r] = c_zero<M>();
       if (live && i >= j && i < N) {
-        vi[r] = (i == j) ? v0 : cload<M>(QR, E, long(i) * n + j);
+        if (i == j) vi[r] = v0;
         const mdc<M> t = c_mul<M>(c_conj<M>(vi[r]), g[r]);
         w = first ? t : c_add<M>(w, t);
         first = false;
