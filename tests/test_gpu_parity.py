@@ -467,7 +467,7 @@ def test_batch_graph_replays(B):
             assert np.array_equal(host(batch.x(p)), eager[p]), (rep, p)
 
 
-@pytest.mark.skip(reason="stalled on the GPU box twice without a cause found in the code yet; "
+@pytest.mark.skip(reason="stalled twice on the GPU without a cause found in the code yet; "
                          "kept off the GPU until one is shown")
 def test_batch_flags_paths_above_64_unknowns(B):
     paths = small_batch(count=3, seed=2)
