@@ -130,7 +130,7 @@ static md_t md_neg(int m, md_t a)
     return a;
 }
 
-/* K terms -> m limbs (K >= m+1). */
+/* K terms -> m limbs (K >= m). */
 static md_t renorm(int m, const double *x, int K)
 {
     double t[TERMS_MAX];
@@ -140,10 +140,21 @@ static md_t renorm(int m, const double *x, int K)
     t[0] = s;
     double e = t[0];
     for (int i = 0; i < m - 1; ++i) two_sum(e, t[i + 1], &y.v[i], &e);
-    double tail = t[K - 1];
-    for (int i = K - 2; i >= m; --i) tail = hadd(tail, t[i]);
-    y.v[m - 1] = hadd(e, tail);
+    if (K > m) {
+        double tail = t[K - 1];
+        for (int i = K - 2; i >= m; --i) tail = hadd(tail, t[i]);
+        e = hadd(e, tail);
+    }
+    y.v[m - 1] = e;
     return y;
+}
+
+/* plain left-to-right sum of n terms */
+static double plain_sum(const double *x, int n)
+{
+    double s = x[0];
+    for (int i = 1; i < n; ++i) s = hadd(s, x[i]);
+    return s;
 }
 
 static md_t add_(int m, md_t a, md_t b)
@@ -165,7 +176,9 @@ static md_t add_(int m, md_t a, md_t b)
         z.v[1] = e;
         return z;
     }
-    /* level i holds a_i, b_i and the errors carried from level i-1 */
+    /* level i holds a_i, b_i and the errors carried from level i-1; the last
+       level is summed in plain arithmetic (its rounding errors lie below
+       the last limb) */
     double carry[MDMAX + 1], c[MDMAX + 1];
     int nc = 0;
     for (int i = 0; i < m; ++i) {
@@ -174,15 +187,16 @@ static md_t add_(int m, md_t a, md_t b)
         terms[nt++] = a.v[i];
         terms[nt++] = b.v[i];
         for (int q = 0; q < nc; ++q) terms[nt++] = carry[q];
+        if (i == m - 1) {
+            c[i] = plain_sum(terms, nt);
+            break;
+        }
         double s = terms[0];
         nc = 0;
         for (int q = 1; q < nt; ++q) two_sum(s, terms[q], &s, &carry[nc++]);
         c[i] = s;
     }
-    double acc = carry[0];
-    for (int q = 1; q < nc; ++q) acc = hadd(acc, carry[q]);
-    c[m] = acc;
-    return renorm(m, c, m + 1);
+    return renorm(m, c, m);
 }
 
 static md_t mul_(int m, md_t a, md_t b)
@@ -204,11 +218,22 @@ static md_t mul_(int m, md_t a, md_t b)
         z.v[1] = e;
         return z;
     }
+    /* level k: the products a_i b_{k-i}, the low parts of level k-1's
+       products and the carries of level k-1; the last level takes plain
+       products and a plain sum (its rounding errors lie below the last
+       limb) */
     double carry[TERMS_MAX], lo[MDMAX + 1], c[MDMAX + 1];
     int nc = 0, nlo = 0;
     for (int k = 0; k < m; ++k) {
         double terms[TERMS_MAX], newlo[MDMAX + 1];
         int nt = 0;
+        if (k == m - 1) {
+            for (int i = 0; i <= k; ++i) terms[nt++] = hmul(a.v[i], b.v[k - i]);
+            for (int i = 0; i < nlo; ++i) terms[nt++] = lo[i];
+            for (int i = 0; i < nc; ++i) terms[nt++] = carry[i];
+            c[k] = plain_sum(terms, nt);
+            break;
+        }
         for (int i = 0; i <= k; ++i) two_prod(a.v[i], b.v[k - i], &terms[nt++], &newlo[i]);
         for (int i = 0; i < nlo; ++i) terms[nt++] = lo[i];
         for (int i = 0; i < nc; ++i) terms[nt++] = carry[i];
@@ -219,12 +244,7 @@ static md_t mul_(int m, md_t a, md_t b)
         for (int i = 0; i <= k; ++i) lo[i] = newlo[i];
         nlo = k + 1;
     }
-    double acc = hmul(a.v[1], b.v[m - 1]);
-    for (int i = 2; i <= m - 1; ++i) acc = hadd(acc, hmul(a.v[i], b.v[m - i]));
-    for (int i = 0; i < nlo; ++i) acc = hadd(acc, lo[i]);
-    for (int i = 0; i < nc; ++i) acc = hadd(acc, carry[i]);
-    c[m] = acc;
-    return renorm(m, c, m + 1);
+    return renorm(m, c, m);
 }
 
 /* multiple double times hardware double */
@@ -235,9 +255,11 @@ static md_t muld_(int m, md_t a, double b)
         z.v[0] = hmul(a.v[0], b);
         return z;
     }
-    /* level i holds p_i, q_{i-1} (a_i b = p_i + q_i exactly) and the carries */
+    /* level i holds p_i, q_{i-1} (a_i b = p_i + q_i exactly) and the
+       carries; the last level takes a plain product and a plain sum */
     double p[MDMAX], q[MDMAX], carry[MDMAX + 1], c[MDMAX + 1];
-    for (int i = 0; i < m; ++i) two_prod(a.v[i], b, &p[i], &q[i]);
+    for (int i = 0; i < m - 1; ++i) two_prod(a.v[i], b, &p[i], &q[i]);
+    p[m - 1] = hmul(a.v[m - 1], b);
     c[0] = p[0];
     int nc = 0;
     for (int i = 1; i < m; ++i) {
@@ -246,15 +268,16 @@ static md_t muld_(int m, md_t a, double b)
         terms[nt++] = p[i];
         terms[nt++] = q[i - 1];
         for (int r = 0; r < nc; ++r) terms[nt++] = carry[r];
+        if (i == m - 1) {
+            c[i] = plain_sum(terms, nt);
+            break;
+        }
         double s = terms[0];
         nc = 0;
         for (int r = 1; r < nt; ++r) two_sum(s, terms[r], &s, &carry[nc++]);
         c[i] = s;
     }
-    double acc = q[m - 1];
-    for (int r = 0; r < nc; ++r) acc = hadd(acc, carry[r]);
-    c[m] = acc;
-    return renorm(m, c, m + 1);
+    return renorm(m, c, m);
 }
 
 static md_t div_(int m, md_t a, md_t b)

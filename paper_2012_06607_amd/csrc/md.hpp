@@ -13,18 +13,20 @@
 //           (8 additions and 12 subtractions, Table 1) and the fma product;
 //   M >= 3  addition: level i holds a_i, b_i and the errors carried from
 //           level i-1, summed by a two-sum cascade whose errors go to level
-//           i+1, the level-M carries added in plain arithmetic, then the M+1
-//           level sums renormalised; multiplication: partial products a_i b_j
-//           with i + j < M as exact two-products, summed level by level in the
+//           i+1; the last level (M-1) is summed in plain arithmetic (its
+//           rounding errors lie below the last limb), then the M level sums
+//           are renormalised; multiplication: partial products a_i b_j with
+//           i + j < M-1 as exact two-products, summed level by level in the
 //           same way (level k: the products of level k in order of i, the low
-//           parts of level k-1's products, then the carries), the level-M
-//           products and carries in plain arithmetic;
+//           parts of level k-1's products, then the carries), the last level's
+//           products and sum in plain arithmetic;
 //   division: long division with M+1 quotient digits (Table 1's "/" column);
 //   1/sqrt: Newton steps y += y (1 - a y^2) / 2 from the hardware value,
 //           ceil(log2 M)+1 of them; sqrt(a) = a * (1/sqrt(a)).
-// Renormalisation of K >= M+1 level sums: a bottom-up two-sum sweep, then a
+// Renormalisation of K >= M level sums: a bottom-up two-sum sweep, then a
 // top-down two-sum sweep emitting limbs 0..M-2, the last limb collecting the
-// remaining terms.
+// remaining terms.  Multiple double times double (M >= 2): a_i b = p_i + q_i
+// exactly for i < M-1, the last level plain.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -103,10 +105,10 @@ __device__ __forceinline__ mdr<M> md_neg(const mdr<M> &a) {
   return z;
 }
 
-// K level sums -> M limbs
+// K level sums -> M limbs (K >= M)
 template <int M, int K>
 __device__ __forceinline__ mdr<M> renorm(const double (&x)[K]) {
-  static_assert(K >= M + 1, "renorm needs K >= M+1");
+  static_assert(K >= M, "renorm needs K >= M");
   double t[K];
   double s = x[K - 1];
   static_for<0, K - 1>([&](auto j) {
@@ -126,12 +128,15 @@ __device__ __forceinline__ mdr<M> renorm(const double (&x)[K]) {
     y.v[i] = r;
     e = ne;
   });
-  double tail = t[K - 1];
-  static_for<0, K - 1 - M>([&](auto j) {
-    constexpr int i = K - 2 - decltype(j)::value;
-    tail = tail + t[i];
-  });
-  y.v[M - 1] = e + tail;
+  if constexpr (K > M) {
+    double tail = t[K - 1];
+    static_for<0, K - 1 - M>([&](auto j) {
+      constexpr int i = K - 2 - decltype(j)::value;
+      tail = tail + t[i];
+    });
+    e = e + tail;
+  }
+  y.v[M - 1] = e;
   return y;
 }
 
@@ -163,32 +168,36 @@ __device__ __forceinline__ mdr<M> md_add(const mdr<M> &a, const mdr<M> &b) {
     return z;
   } else {
     double carry[M + 1];
-    double c[M + 1];
+    double c[M];
     static_for<0, M>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
       // terms: a_i, b_i, carry[0..i-1]
-      double s = a.v[i];
-      double nc[M + 1];
-      {
-        double ns, e;
-        two_sum(s, b.v[i], ns, e);
-        s = ns;
-        nc[0] = e;
+      if constexpr (i == M - 1) {
+        // the last level in plain arithmetic
+        double s = a.v[i] + b.v[i];
+        static_for<0, i>([&](auto qc) { s = s + carry[decltype(qc)::value]; });
+        c[i] = s;
+      } else {
+        double s = a.v[i];
+        double nc[M + 1];
+        {
+          double ns, e;
+          two_sum(s, b.v[i], ns, e);
+          s = ns;
+          nc[0] = e;
+        }
+        static_for<0, i>([&](auto qc) {
+          constexpr int q = decltype(qc)::value;
+          double ns, e;
+          two_sum(s, carry[q], ns, e);
+          s = ns;
+          nc[q + 1] = e;
+        });
+        c[i] = s;
+        static_for<0, i + 1>([&](auto qc) { carry[decltype(qc)::value] = nc[decltype(qc)::value]; });
       }
-      static_for<0, i>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        double ns, e;
-        two_sum(s, carry[q], ns, e);
-        s = ns;
-        nc[q + 1] = e;
-      });
-      c[i] = s;
-      static_for<0, i + 1>([&](auto qc) { carry[decltype(qc)::value] = nc[decltype(qc)::value]; });
     });
-    double acc = carry[0];
-    static_for<1, M>([&](auto qc) { acc = acc + carry[decltype(qc)::value]; });
-    c[M] = acc;
-    return renorm<M, M + 1>(c);
+    return renorm<M, M>(c);
   }
 }
 
@@ -219,46 +228,49 @@ __device__ __forceinline__ mdr<M> md_mul(const mdr<M> &a, const mdr<M> &b) {
     constexpr int CMAX = mul_level_terms(M - 1);
     double carry[CMAX];
     double lo[M];
-    double c[M + 1];
+    double c[M];
     static_for<0, M>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
       constexpr int ncar = (k == 0) ? 0 : mul_level_terms(k - 1) - 1;
       constexpr int nt = (k + 1) + k + ncar;
-      double terms[CMAX];
-      double newlo[M];
-      static_for<0, k + 1>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        two_prod(a.v[i], b.v[k - i], terms[i], newlo[i]);
-      });
-      static_for<0, k>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        terms[k + 1 + i] = lo[i];
-      });
-      static_for<0, ncar>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        terms[2 * k + 1 + i] = carry[i];
-      });
-      double s = terms[0];
-      static_for<1, nt>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        double ns, e;
-        two_sum(s, terms[i], ns, e);
-        s = ns;
-        carry[i - 1] = e;
-      });
-      c[k] = s;
-      static_for<0, k + 1>([&](auto ic) { lo[decltype(ic)::value] = newlo[decltype(ic)::value]; });
+      if constexpr (k == M - 1) {
+        // the last level: plain products and a plain sum
+        double s = a.v[0] * b.v[k];
+        static_for<1, k + 1>([&](auto ic) {
+          constexpr int i = decltype(ic)::value;
+          s = s + a.v[i] * b.v[k - i];
+        });
+        static_for<0, k>([&](auto ic) { s = s + lo[decltype(ic)::value]; });
+        static_for<0, ncar>([&](auto ic) { s = s + carry[decltype(ic)::value]; });
+        c[k] = s;
+      } else {
+        double terms[CMAX];
+        double newlo[M];
+        static_for<0, k + 1>([&](auto ic) {
+          constexpr int i = decltype(ic)::value;
+          two_prod(a.v[i], b.v[k - i], terms[i], newlo[i]);
+        });
+        static_for<0, k>([&](auto ic) {
+          constexpr int i = decltype(ic)::value;
+          terms[k + 1 + i] = lo[i];
+        });
+        static_for<0, ncar>([&](auto ic) {
+          constexpr int i = decltype(ic)::value;
+          terms[2 * k + 1 + i] = carry[i];
+        });
+        double s = terms[0];
+        static_for<1, nt>([&](auto ic) {
+          constexpr int i = decltype(ic)::value;
+          double ns, e;
+          two_sum(s, terms[i], ns, e);
+          s = ns;
+          carry[i - 1] = e;
+        });
+        c[k] = s;
+        static_for<0, k + 1>([&](auto ic) { lo[decltype(ic)::value] = newlo[decltype(ic)::value]; });
+      }
     });
-    double acc = a.v[1] * b.v[M - 1];
-    static_for<2, M>([&](auto ic) {
-      constexpr int i = decltype(ic)::value;
-      acc = acc + a.v[i] * b.v[M - i];
-    });
-    static_for<0, M>([&](auto ic) { acc = acc + lo[decltype(ic)::value]; });
-    constexpr int ncl = mul_level_terms(M - 1) - 1;
-    static_for<0, ncl>([&](auto ic) { acc = acc + carry[decltype(ic)::value]; });
-    c[M] = acc;
-    return renorm<M, M + 1>(c);
+    return renorm<M, M>(c);
   }
 }
 
@@ -271,38 +283,43 @@ __device__ __forceinline__ mdr<M> md_muld(const mdr<M> &a, double b) {
     return z;
   } else {
     double p[M], q[M];
-    static_for<0, M>([&](auto ic) {
+    static_for<0, M - 1>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
       two_prod(a.v[i], b, p[i], q[i]);
     });
-    double c[M + 1];
+    p[M - 1] = a.v[M - 1] * b;
+    double c[M];
     double carry[M];
     c[0] = p[0];
     static_for<1, M>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
       // terms: p_i, q_{i-1}, carry[0..i-2]
-      double s = p[i];
-      double nc[M];
-      {
-        double ns, e;
-        two_sum(s, q[i - 1], ns, e);
-        s = ns;
-        nc[0] = e;
+      if constexpr (i == M - 1) {
+        // the last level in plain arithmetic
+        double s = p[i] + q[i - 1];
+        static_for<0, i - 1>([&](auto rc) { s = s + carry[decltype(rc)::value]; });
+        c[i] = s;
+      } else {
+        double s = p[i];
+        double nc[M];
+        {
+          double ns, e;
+          two_sum(s, q[i - 1], ns, e);
+          s = ns;
+          nc[0] = e;
+        }
+        static_for<0, i - 1>([&](auto rc) {
+          constexpr int r = decltype(rc)::value;
+          double ns, e;
+          two_sum(s, carry[r], ns, e);
+          s = ns;
+          nc[r + 1] = e;
+        });
+        c[i] = s;
+        static_for<0, i>([&](auto rc) { carry[decltype(rc)::value] = nc[decltype(rc)::value]; });
       }
-      static_for<0, i - 1>([&](auto rc) {
-        constexpr int r = decltype(rc)::value;
-        double ns, e;
-        two_sum(s, carry[r], ns, e);
-        s = ns;
-        nc[r + 1] = e;
-      });
-      c[i] = s;
-      static_for<0, i>([&](auto rc) { carry[decltype(rc)::value] = nc[decltype(rc)::value]; });
     });
-    double acc = q[M - 1];
-    static_for<0, M - 1>([&](auto rc) { acc = acc + carry[decltype(rc)::value]; });
-    c[M] = acc;
-    return renorm<M, M + 1>(c);
+    return renorm<M, M>(c);
   }
 }
 
