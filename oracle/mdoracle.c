@@ -27,20 +27,21 @@
  *          add row (8 additions, 12 subtractions), and the fma product;
  *   m >= 3 addition: level i holds a_i, b_i and the errors carried from
  *          level i-1, summed by a two-sum cascade whose errors go to level
- *          i+1; the level-m carries are added in plain arithmetic, then
- *          the m+1 level sums are renormalised; multiplication: all partial
- *          products a_i b_j
- *          with i + j < m as exact two-products, summed level by level with
- *          two-sum cascades whose errors are carried to the next level, the
- *          level-m products and carries added in plain arithmetic, then
- *          renormalised;
+ *          i+1; the last level (m-1) is summed in plain arithmetic (its
+ *          rounding errors lie below the last limb), then the m level sums
+ *          are renormalised; multiplication: the partial products a_i b_j
+ *          with i + j < m-1 as exact two-products, summed level by level
+ *          with two-sum cascades whose errors are carried to the next level,
+ *          the products of level m-1 and the carries into it summed in
+ *          plain arithmetic, then renormalised;
  *   division: long division with m+1 quotient digits, each one hardware
  *          division (Table 1's "/" column is m+1 for every m);
  *   square root: Newton iteration for 1/sqrt(a) from the hardware value,
  *          ceil(log2 m)+1 steps, then sqrt(a) = a * (1/sqrt(a)).
- * Multiple double times double: a_i b = p_i + q_i exactly; level i holds
- * p_i, q_{i-1} and the carries, summed as in the addition.
- * Renormalisation of K >= m+1 terms, one per level: a bottom-up two-sum
+ * Multiple double times double: a_i b = p_i + q_i exactly for i < m-1 and
+ * a plain product at i = m-1; level i holds p_i, q_{i-1} and the carries,
+ * summed as in the addition.
+ * Renormalisation of K >= m terms, one per level: a bottom-up two-sum
  * sweep (error free), then a top-down two-sum sweep that emits limbs
  * 0..m-2, the last limb collecting the rest.
  *
