@@ -79,6 +79,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall time budget of the CPU oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-workers", type=int, default=min(16, os.cpu_count() or 1),
+                    help="oracle worker processes of the CPU baseline (default: the host's "
+                         "cores, at most 16)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the launch-shape tuner (512 threads, one workgroup per CU)")
     ap.add_argument("--gang-factor", type=float, default=None,
@@ -108,29 +111,57 @@ def make_paths(count):
     return paths
 
 
-def cpu_baseline(paths, budget_s: float) -> dict:
-    """The oracle, single threaded, on a sample of the same paths (every
-    path in turn from a stride through the batch, 4 Newton steps each)
-    until the time budget is spent; Newton steps per second."""
+_POOL = {}
+
+
+def _oracle_worker(w: int):
+    """One worker of the CPU baseline: take the next job from the shared
+    counter (job j is path 37 j mod the batch size), run ITERS oracle Newton
+    steps on it, until the time budget is spent; returns (steps, seconds,
+    paths done)."""
     import oracle
-    oracle.build()
-    stride = 37                           # coprime with the batch size: mixes n, d, m
+    paths, counter, budget, stride = (_POOL[k] for k in ("paths", "counter", "budget", "stride"))
     t0 = time.perf_counter()
     steps, done = 0, []
-    p = 0
-    while True:
-        sysm, x = paths[p % len(paths)]
+    while time.perf_counter() - t0 < budget:
+        with counter.get_lock():
+            j = counter.value
+            counter.value += 1
+        q = (j * stride) % len(paths)
+        sysm, x = paths[q]
         oracle.newton(sysm, x, ITERS)
         steps += ITERS
-        done.append(p % len(paths))
-        p += stride
-        el = time.perf_counter() - t0
-        if el >= budget_s:
-            break
+        done.append(q)
+    return steps, time.perf_counter() - t0, done
+
+
+def cpu_baseline(paths, budget_s: float, workers: int) -> dict:
+    """The oracle on a sample of the same paths: `workers` processes take
+    paths from one shared job counter (the job queue of Section 5), each
+    path ITERS Newton steps, until the time budget is spent.  The rate is
+    the sum of the workers' own rates (steps over each worker's busy time).
+    Runs before anything touches the GPU: the workers are forked."""
+    import multiprocessing as mp
+
+    import oracle
+    oracle.build()
+    oracle.lib()
+    ctx = mp.get_context("fork")
+    _POOL.update(paths=paths, counter=ctx.Value("i", 0), budget=budget_s, stride=37)
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        res = pool.map(_oracle_worker, range(workers), chunksize=1)
+    wall = time.perf_counter() - t0
+    steps = sum(r[0] for r in res)
+    rate = sum(r[0] / r[1] for r in res if r[1] > 0)
+    done = sorted({q for r in res for q in r[2]})
     ns = sorted({paths[q][0].n for q in done})
-    return {"value": round(steps / el, 3), "unit": "Newton steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{len(done)} paths of the batch (every {stride}th, n in {ns}), "
-                      f"{ITERS} Newton steps each, {el:.1f} s on one host thread, gcc -O2 C oracle"}
+    ms = sorted({paths[q][0].m for q in done})
+    return {"value": round(rate, 3), "unit": "Newton steps/s", "cores": workers, "kind": "oracle",
+            "sample": f"{len(done)} paths of the batch (job j = path 37 j mod {len(paths)}; n in "
+                      f"{ns}, m in {ms}), {ITERS} Newton steps each, {steps} steps in {wall:.1f} s "
+                      f"wall on {workers} worker processes sharing one job counter; gcc -O2 C "
+                      f"oracle; rate = sum of per-worker steps/busy seconds"}
 
 
 def batched(args, B, OC, paths):
@@ -353,14 +384,21 @@ def main():
               f"multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import torch
+    if torch.cuda.device_count() < 1:   # counts devices without initialising one
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    paths = make_paths(args.paths)
+    cpu = None
+    if not args.no_cpu_baseline:
+        # before the GPU is initialised, so that the oracle workers can be forked
+        cpu = cpu_baseline(paths, args.cpu_seconds, args.cpu_workers)
+
     from paper_2012_06607_amd import binding as B
     from paper_2012_06607_amd import opcount as OC
-
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     B.lib()
-    paths = make_paths(args.paths)
     if args.copy_mib > 0:
         src = torch.ones(args.copy_mib << 17, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -416,8 +454,8 @@ def main():
         line["single_path"] = single_path(args, B, OC)
     if not args.no_adjoint:
         line["adjoint"] = adjoint_measure(args, B, OC)
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(paths, args.cpu_seconds)
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 
 
