@@ -92,6 +92,9 @@ def parse():
     ap.add_argument("--no-single", action="store_true",
                     help="skip the single-path step (32 unknowns, d = 16, quad double)")
     ap.add_argument("--single-steps", type=int, default=50)
+    ap.add_argument("--no-high-precision", action="store_true",
+                    help="skip the octo / deca double step at 64 unknowns, d = 32")
+    ap.add_argument("--hp-reps", type=int, default=3)
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint measurement (32 unknowns, d = 16, quad double)")
     ap.add_argument("--adj-reps", type=int, default=20)
@@ -247,29 +250,29 @@ def batched(args, B, OC, paths):
     return res
 
 
-def single_path(args, B, OC) -> dict:
-    """The 32-unknown quad-double step on one path: md_poly_eval_diff on a
-    32 x 32 system (16 monomials of degree <= 4 per equation) at a unit
-    series point, md_qr of a 32 x 32 A_0 with condition number 1e3, and
-    md_series_solve with d = 16."""
+def solve_eval(B, OC, m: int, n: int, d: int, key: int, reps: int, warm: int) -> dict:
+    """One path's linear-algebra step at m limbs: md_poly_eval_diff on an
+    n x n system (16 monomials of degree <= 4 per equation) at a unit
+    series point, md_qr of an n x n A_0 with condition number 1e3, and
+    md_series_solve at degree d; mean of `reps` timed repetitions."""
     import numpy as np
     import torch
     from paper_2012_06607_amd import inputs as I
-    sysm = I.eval_system((2, 0), N1, N1, M1, 16, 4)
-    x = torch.as_tensor(I.unit_series((2, 1), M1, D1, N1), device="cuda")
-    A_h, b_h = I.toeplitz_system((2, N1), N1, D1, M1)
+    sysm = I.eval_system((key, 0), n, n, m, 16, 4)
+    x = torch.as_tensor(I.unit_series((key, 1), m, d, n), device="cuda")
+    A_h, b_h = I.toeplitz_system((key, n), n, d, m)
     A = torch.as_tensor(A_h, device="cuda")
     b = torch.as_tensor(b_h, device="cuda")
     sd = B.DeviceSystem(sysm)
     A0 = A[:, :, 0].contiguous()
-    f = torch.empty((2, M1, D1 + 1, N1), dtype=torch.float64, device="cuda")
-    Aev = torch.empty((2, M1, D1 + 1, N1, N1), dtype=torch.float64, device="cuda")
-    dx = torch.empty((2, M1, D1 + 1, N1), dtype=torch.float64, device="cuda")
-    ws_eval = B.workspace(B.MD_FN_EVAL, M1, N1, N1, D1, sysm.M, sysm.max_deg)
-    ws_solve = B.workspace(B.MD_FN_SOLVE, M1, N1, N1, D1, 0, 0)
+    f = torch.empty((2, m, d + 1, n), dtype=torch.float64, device="cuda")
+    Aev = torch.empty((2, m, d + 1, n, n), dtype=torch.float64, device="cuda")
+    dx = torch.empty((2, m, d + 1, n), dtype=torch.float64, device="cuda")
+    ws_eval = B.workspace(B.MD_FN_EVAL, m, n, n, d, sysm.M, sysm.max_deg)
+    ws_solve = B.workspace(B.MD_FN_SOLVE, m, n, n, d, 0, 0)
     QRb = torch.empty_like(A0)
-    vdb = torch.empty((2, M1, N1), dtype=torch.float64, device="cuda")
-    betab = torch.empty((M1, N1), dtype=torch.float64, device="cuda")
+    vdb = torch.empty((2, m, n), dtype=torch.float64, device="cuda")
+    betab = torch.empty((m, n), dtype=torch.float64, device="cuda")
     status = torch.zeros(1, dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
 
@@ -286,24 +289,30 @@ def single_path(args, B, OC) -> dict:
         if ev is not None:
             ev[3].record(stream)
 
-    for _ in range(5):
+    for _ in range(warm):
         step()
-    K = args.single_steps
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(reps)]
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0.record(stream)
-    for s in range(K):
-        step(evs[s])
+    for r in range(reps):
+        step(evs[r])
     t1.record(stream)
     torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1) / K
+    ms = t0.elapsed_time(t1) / reps
     names = ("md_poly_eval_diff", "md_qr", "md_series_solve")
-    dur = {nm: float(np.mean([evs[s][i].elapsed_time(evs[s][i + 1]) for s in range(K)]))
+    dur = {nm: float(np.mean([evs[r][i].elapsed_time(evs[r][i + 1]) for r in range(reps)]))
            for i, nm in enumerate(names)}
-    ops = {"md_poly_eval_diff": OC.eval_diff(sysm, D1).table_ops(M1),
-           "md_qr": OC.qr(N1, N1, M1).table_ops(M1),
-           "md_series_solve": OC.series_solve(N1, N1, D1).table_ops(M1)}
+    ops = {"md_poly_eval_diff": OC.eval_diff(sysm, d).table_ops(m),
+           "md_qr": OC.qr(n, n, m).table_ops(m),
+           "md_series_solve": OC.series_solve(n, n, d).table_ops(m)}
+    return {"ms": ms, "dur": dur, "ops": ops, "status": int(status.item())}
+
+
+def single_path(args, B, OC) -> dict:
+    """The 32-unknown quad-double step on one path (d = 16)."""
+    r = solve_eval(B, OC, M1, N1, D1, 2, args.single_steps, 5)
+    ms, dur, ops = r["ms"], r["dur"], r["ops"]
     qr_tf = ops["md_qr"] / (dur["md_qr"] * 1e-3) / 1e12
     return {
         "workload": "qd, n = N = 32, d = 16: eval/diff of a 32x32 system (16 monomials of "
@@ -312,11 +321,57 @@ def single_path(args, B, OC) -> dict:
         "pct_fp64_vector_peak": round(100.0 * sum(ops.values()) / (ms * 1e-3)
                                       / OC.FP64_VECTOR_PEAK, 4),
         "kernels_ms": {k: round(v, 4) for k, v in dur.items()},
+        "evals_per_s": round(1000.0 / dur["md_poly_eval_diff"], 2),
+        "solves_per_s": round(1000.0 / (dur["md_qr"] + dur["md_series_solve"]), 2),
         "k_qr_roofline": {"bound": "alu", "achieved": round(qr_tf, 5), "peak": 78.6,
                           "unit": "TFLOP/s", "frac": round(qr_tf / 78.6, 6),
                           "traffic": traffic_bytes("k_qr")},
-        "status": int(status.item()),
+        "status": r["status"],
     }
+
+
+def high_precision(args, B, OC) -> dict:
+    """Octo and deca double at n = 64, d = 32: the eval + QR + solve of one
+    path, the 2-norm of 64 unit complex numbers (Section 2: exactly 8) and
+    64 series products of 33 coefficients."""
+    import torch
+    from paper_2012_06607_amd import inputs as I
+    out = {"workload": "od and da, n = N = 64, d = 32: eval/diff of a 64x64 system (16 "
+                       "monomials of degree <= 4 per equation) + QR of A_0 (cond 1e3) + "
+                       "staggered solve; 2-norm of 64 unit complex numbers; 64 convolutions "
+                       "of 33-coefficient series"}
+    stream = torch.cuda.current_stream()
+    for m, name in ((8, "od"), (10, "da")):
+        r = solve_eval(B, OC, m, 64, 32, 3, args.hp_reps, 1)
+        ms, dur, ops = r["ms"], r["dur"], r["ops"]
+        xs = torch.as_tensor(I.unit_complex(I.rng(3, m, 1), m, 64, 33), device="cuda")
+        ys = torch.as_tensor(I.unit_complex(I.rng(3, m, 2), m, 64, 33), device="cuda")
+        z = B.md_series_convolve(xs, ys)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(10):
+            B.md_series_convolve(xs, ys, z)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        conv_ms = e0.elapsed_time(e1) / 10
+        conv_ops = OC.convolve(32, 64).table_ops(m)
+        nrm = B.md_norm2(torch.as_tensor(I.unit_complex(I.rng(951, m), m, 64), device="cuda"))
+        torch.cuda.synchronize()
+        out[name] = {
+            "ms_per_step": round(ms, 3),
+            "kernels_ms": {k: round(v, 3) for k, v in dur.items()},
+            "evals_per_s": round(1000.0 / dur["md_poly_eval_diff"], 2),
+            "solves_per_s": round(1000.0 / (dur["md_qr"] + dur["md_series_solve"]), 2),
+            "pct_fp64_vector_peak": round(100.0 * sum(ops.values()) / (ms * 1e-3)
+                                          / OC.FP64_VECTOR_PEAK, 4),
+            "convolve_64x33_ms": round(conv_ms, 4),
+            "convolve_pct_fp64_vector_peak": round(100.0 * conv_ops / (conv_ms * 1e-3)
+                                                   / OC.FP64_VECTOR_PEAK, 3),
+            "norm2_of_64_unit_numbers_limb0": float(nrm[0, 0].item()),
+            "status": r["status"],
+        }
+    return out
 
 
 def adjoint_measure(args, B, OC) -> dict:
@@ -454,6 +509,8 @@ def main():
         line["single_path"] = single_path(args, B, OC)
     if not args.no_adjoint:
         line["adjoint"] = adjoint_measure(args, B, OC)
+    if not args.no_high_precision:
+        line["high_precision"] = high_precision(args, B, OC)
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
