@@ -30,12 +30,11 @@ FLAGS = [
 ]
 
 
-# Device functions allowed to stay real calls: leaf routines without LDS
-# variables of their own.  Everything else must be inlined into its kernel:
-# a call into a large function has shown two hazards here, long jumps that
-# go through s[30:31] (the return address) and wrong results from a
-# non-inlined function that declares LDS variables.
-CALLABLE = (re.compile(r"^_ZN3mds10conv_group"),)
+# Every device function must be inlined into its kernel: a call into a large
+# function has shown two hazards here, long jumps that go through s[30:31]
+# (the return address) and wrong results from a non-inlined function that
+# declares LDS variables.  Patterns of functions allowed to stay calls:
+CALLABLE: tuple = ()
 
 
 def check_device_asm(asm_path: str) -> list[str]:

@@ -502,7 +502,7 @@ __device__ __forceinline__ mdc<M> conv_part(const mdc<M> *X, int dx, const mdc<M
 // fewer coefficients than a group has lanes, each lane takes whole
 // coefficients instead.  Called by all 64 lanes of a wave.
 template <int M>
-__device__ __noinline__ void conv_group(const mdc<M> *X, int dx, const mdc<M> *Y, mdc<M> *Z,
+__device__ __forceinline__ void conv_group(const mdc<M> *X, int dx, const mdc<M> *Y, mdc<M> *Z,
                                            int d, int r, double *ws, long Ews, long wbase,
                                            int mult) {
   const int lane = lane_id();
