@@ -583,14 +583,56 @@ __device__ __forceinline__ void eval_term_wave(const EvalArgs &a, int tau, int r
       cstore<M>(a.ws, a.Ews, wb + a.lay.val() * L + k, S(T.cs())[k]);
     return;
   }
-  if (D == 1) {
-    conv_group<M>(S(T.cs()), dcu, S(T.xs(0)), nullptr, d, r, a.ws, a.Ews, wb + a.lay.val() * L, 1);
-    for (int k = lane; k < L; k += WAVE)
-      cstore<M>(a.ws, a.Ews, wb + a.lay.der(1) * L + k, S(T.cs())[k]);
-    return;
-  }
   auto Pj = [&](int j) { return j == 1 ? S(T.xs(0)) : S(T.P(j)); };
   auto Qj = [&](int j) { return j == D ? S(T.xs(D - 1)) : S(T.Q(j)); };
+  // c(t) times the value (slot 0) and the derivatives (slot j: the cross
+  // product of the j-th factor's first occurrence times its multiplicity).
+  // With a short coefficient series (dcu < r) every lane takes whole
+  // (slot, coefficient) pairs of all slots at once, each sum in the order
+  // of conv_part; otherwise the slots go one by one through the lane groups.
+  auto coef_products = [&]() __attribute__((always_inline)) {
+    if (dcu < r) {
+      for (int e = lane; e < (D + 1) * L; e += WAVE) {
+        const int j = e / L, k = e - j * L;
+        if (j > 1 && v[j - 1] == v[j - 2]) continue;
+        mdc<M> z;
+        if (D == 1 && j == 1) {
+          z = S(T.cs())[k];  // d(c x)/dx = c
+        } else {
+          const mdc<M> *Y = j == 0 ? Pj(D) : (j == 1 ? Qj(2) : (j == D ? Pj(D - 1) : S(T.C(j))));
+          z = conv_part<M>(S(T.cs()), dcu, Y, k, 0, 1);
+          int mult = 1;
+          if (j > 0) {
+            mult = 0;
+            for (int q = 0; q < D; ++q) mult += (v[q] == v[j - 1]);
+          }
+          if (mult > 1) {
+            z.re = md_muld<M>(z.re, double(mult));
+            z.im = md_muld<M>(z.im, double(mult));
+          }
+        }
+        cstore<M>(a.ws, a.Ews, wb + (j == 0 ? a.lay.val() : a.lay.der(j)) * L + k, z);
+      }
+      return;
+    }
+    conv_group<M>(S(T.cs()), dcu, Pj(D), nullptr, d, r, a.ws, a.Ews, wb + a.lay.val() * L, 1);
+    if (D == 1) {
+      for (int k = lane; k < L; k += WAVE)
+        cstore<M>(a.ws, a.Ews, wb + a.lay.der(1) * L + k, S(T.cs())[k]);
+      return;
+    }
+    for (int j = 1; j <= D; ++j) {
+      if (j > 1 && v[j - 1] == v[j - 2]) continue;
+      int mult = 0;
+      for (int q = 0; q < D; ++q) mult += (v[q] == v[j - 1]);
+      const mdc<M> *cross = (j == 1) ? Qj(2) : (j == D ? Pj(D - 1) : S(T.C(j)));
+      conv_group<M>(S(T.cs()), dcu, cross, nullptr, d, r, a.ws, a.Ews, wb + a.lay.der(j) * L, mult);
+    }
+  };
+  if (D == 1) {
+    coef_products();
+    return;
+  }
   for (int st = 1; st <= D - 1; ++st) {
     conv_group<M>(Pj(st), d, S(T.xs(st)), S(T.P(st + 1)), d, r, nullptr, 0, 0, 1);
     const int j = D - st;
@@ -603,14 +645,7 @@ __device__ __forceinline__ void eval_term_wave(const EvalArgs &a, int tau, int r
   if (a.mono)
     for (int k = lane; k < L; k += WAVE) cstore<M>(a.mono, Em, long(tau) * L + k, Pj(D)[k]);
   wave_sync();
-  conv_group<M>(S(T.cs()), dcu, Pj(D), nullptr, d, r, a.ws, a.Ews, wb + a.lay.val() * L, 1);
-  for (int j = 1; j <= D; ++j) {
-    if (j > 1 && v[j - 1] == v[j - 2]) continue;
-    int mult = 0;
-    for (int q = 0; q < D; ++q) mult += (v[q] == v[j - 1]);
-    const mdc<M> *cross = (j == 1) ? Qj(2) : (j == D ? Pj(D - 1) : S(T.C(j)));
-    conv_group<M>(S(T.cs()), dcu, cross, nullptr, d, r, a.ws, a.Ews, wb + a.lay.der(j) * L, mult);
-  }
+  coef_products();
 }
 
 // f_i[k] (g's l == n) or A_{i,l}[k], one element per call (g over
