@@ -126,7 +126,7 @@ __device__ __forceinline__ void newton_path(const md_path &p, int iters, const i
   a.A = A;
   const int seg_q = pow2_at_least((N + 1) / 2);  // QR: two rows per lane
   const int seg_dx = dot_seg_throughput(N), seg_up = dot_seg_throughput(n);
-  const int seg_p = pow2_at_least((N + 1) / 2);  // R^{-1} Q^H: two rows per lane
+  const int seg_p = pow2_at_least((N + 3) / 4);  // R^{-1} Q^H: four rows per lane
   const int spw_p = WAVE / seg_p, nslots_p = nwaves * spw_p;
   const int slot_p = wave * spw_p + lane_id() / seg_p;
   const int spw_x = WAVE / seg_dx, nslots_x = nwaves * spw_x;
@@ -165,7 +165,7 @@ __device__ __forceinline__ void newton_path(const md_path &p, int iters, const i
     gsync();
     for (int base = member * nslots_p; base < N; base += G * nslots_p) {
       const int c = base + slot_p;
-      pinv_column<M, 2>(c < N, c, N, n, seg_p, QR, vd, beta, invd, W);
+      pinv_column<M, 4>(c < N, c, N, n, seg_p, QR, vd, beta, invd, W);
     }
     gsync();
     // staggered substitution: every member forms dx_k, the updates of the

@@ -310,40 +310,52 @@ __device__ __forceinline__ void pinv_column(bool live, int c, int N, int n, int 
       if (live && i > j && i < N) vi[r] = cload<M>(QR, E, long(i) * n + j);
     }
   };
-  mdc<M> v0n, vin[RPL];
+  // with four or more rows per lane and no prefetch the reflector's rows are
+  // not held in registers: each is read where it is used (twice, through L1)
+  constexpr bool HOLD = RPL < 4 || PF;
+  mdc<M> v0n, vin[HOLD ? RPL : 1];
   mdr<M> betn;
-  if (PF && n > 0) load_v(0, v0n, betn, vin);
+  if constexpr (PF) {
+    if (n > 0) load_v(0, v0n, betn, vin);
+  }
   for (int j = 0; j < n; ++j) {
-    mdc<M> v0, vi[RPL];
+    mdc<M> v0, vi[HOLD ? RPL : 1];
     mdr<M> bet;
-    if (PF) {
+    if constexpr (PF) {
       v0 = v0n;
       bet = betn;
 #pragma unroll
       for (int r = 0; r < RPL; ++r) vi[r] = vin[r];
       if (j + 1 < n) load_v(j + 1, v0n, betn, vin);
-    } else {
+    } else if constexpr (HOLD) {
       load_v(j, v0, bet, vi);
+    } else {
+      v0 = cload<M>(vdiag, n, j);
+      bet = rload<M>(beta, n, j);
     }
+    auto vrow = [&](int r, int i) __attribute__((always_inline)) {
+      if constexpr (HOLD) return i == j ? v0 : vi[r];
+      else return i == j ? v0 : cload<M>(QR, E, long(i) * n + j);
+    };
     mdc<M> w = c_zero<M>();
     bool first = true;
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
       const int i = lis + r * seg;
       if (live && i >= j && i < N) {
-        if (i == j) vi[r] = v0;
-        const mdc<M> t = c_mul<M>(c_conj<M>(vi[r]), g[r]);
+        const mdc<M> t = c_mul<M>(c_conj<M>(vrow(r, i)), g[r]);
         w = first ? t : c_add<M>(w, t);
         first = false;
       }
     }
+    if constexpr (!HOLD) asm volatile("" ::: "memory");  // read the rows again below
     w = seg_reduce_c<M>(w, seg);
     w = shfl_c<M>(w, lane & ~(seg - 1));
     const mdc<M> bw = c_mulr<M>(w, bet);
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
       const int i = lis + r * seg;
-      if (live && i >= j && i < N) g[r] = c_sub<M>(g[r], c_mul<M>(bw, vi[r]));
+      if (live && i >= j && i < N) g[r] = c_sub<M>(g[r], c_mul<M>(bw, vrow(r, i)));
     }
   }
   for (int i = n - 1; i >= 0; --i) {
