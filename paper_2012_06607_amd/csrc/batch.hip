@@ -144,17 +144,15 @@ __device__ __forceinline__ void newton_path(const md_path &p, int iters, const i
   };
   for (int it = 0; it < iters; ++it) {
     // evaluation and differentiation: waves (of all members) over terms,
-    // then the sums, one (equation, coefficient) pair per thread, with
-    // r = -f written by the thread that formed f
+    // then the sums, one (equation, coefficient) pair per lane (each wave
+    // clears its rows of A first), with r = -f written by the lane that
+    // formed f
     if (wave < eval_waves)
       for (int tau = member * eval_waves + wave; tau < p.M; tau += G * eval_waves)
         eval_term_wave<M>(a, tau, rgrp, lds + wave * per_wave, [] { wave_sync(); });
     gsync();
-    for (int g = member * nt + tid; g < L * N; g += G * nt) {
-      const int i = g % N, k = g / N;
-      eval_accumulate_row<M>(a, i, k);
-      cstore<M>(r, Er, long(k) * N + i, c_neg<M>(cload<M>(f, Er, long(k) * N + i)));
-    }
+    for (long g0 = long(member) * nt + wave * WAVE; g0 < long(L) * N; g0 += long(G) * nt)
+      eval_accumulate_wave<M>(a, g0, r, [] { wave_sync(); });
     gsync();
     // QR of A_0 (the k = 0 block of A) on member 0, then W = R^{-1}
     // (Q^H)_{0:n}, columns over all members

@@ -696,13 +696,15 @@ __device__ __forceinline__ void eval_accumulate_elem(const EvalArgs &a, long g) 
 // i added in term order, the value slot into f_i and, for every distinct
 // factor l of a term, its derivative slot (first occurrence of l) into
 // A_{i,l}.  Each sum starts from zero and adds in term order, as the
-// definition reads; entries no term touches stay zero.
+// definition reads; entries no term touches stay zero.  `zeroed`: the row
+// was cleared already.
 template <int M>
-__device__ __forceinline__ void eval_accumulate_row(const EvalArgs &a, int i, int k) {
+__device__ __forceinline__ void eval_accumulate_row(const EvalArgs &a, int i, int k, bool zeroed = false) {
   const int L = a.d + 1;
   const long EA = long(L) * a.N * a.n;
   const long rowA = (long(k) * a.N + i) * a.n;
-  for (int l = 0; l < a.n; ++l) cstore<M>(a.A, EA, rowA + l, c_zero<M>());
+  if (!zeroed)
+    for (int l = 0; l < a.n; ++l) cstore<M>(a.A, EA, rowA + l, c_zero<M>());
   mdc<M> acc = c_zero<M>();
   for (int tau = a.eq_ptr[i]; tau < a.eq_ptr[i + 1]; ++tau) {
     const long wb = long(tau) * a.S * L + k;
@@ -718,6 +720,28 @@ __device__ __forceinline__ void eval_accumulate_row(const EvalArgs &a, int i, in
     }
   }
   cstore<M>(a.f, long(L) * a.N, long(k) * a.N + i, acc);
+}
+
+// Rows g0 .. g0+63 of the Jacobian sums (row g = k N + i) by one wave: the
+// wave clears the rows' A entries together (consecutive lanes, consecutive
+// addresses), then each lane forms its row as eval_accumulate_row and
+// writes r_k[i] = -f_k[i].  All lanes of the wave call this.
+template <int M, class Sync>
+__device__ __forceinline__ void eval_accumulate_wave(const EvalArgs &a, long g0, double *__restrict__ r,
+                                                     Sync wave_sync) {
+  const int L = a.d + 1;
+  const long rows = long(L) * a.N;
+  const long EA = rows * a.n, Er = rows;
+  const int lane = lane_id();
+  const long cnt = rows - g0 < WAVE ? rows - g0 : WAVE;
+  for (long e = lane; e < cnt * a.n; e += WAVE) cstore<M>(a.A, EA, g0 * a.n + e, c_zero<M>());
+  wave_sync();
+  const long g = g0 + lane;
+  if (g < rows) {
+    const int i = int(g % a.N), k = int(g / a.N);
+    eval_accumulate_row<M>(a, i, k, true);
+    cstore<M>(r, Er, g, c_neg<M>(cload<M>(a.f, Er, g)));
+  }
 }
 
 // ---------------------------------------------------------------------------
