@@ -124,7 +124,7 @@ __device__ __forceinline__ void newton_path(const md_path &p, int iters, const i
   a.Ews = a.lay.E;
   a.f = f;
   a.A = A;
-  const int seg_q = pow2_at_least((N + 1) / 2);  // QR: two rows per lane
+  const int seg_q = pow2_at_least((N + 3) / 4);  // QR: four rows per lane
   const int seg_dx = dot_seg_throughput(N), seg_up = dot_seg_throughput(n);
   const int seg_p = pow2_at_least((N + 3) / 4);  // R^{-1} Q^H: four rows per lane
   const int spw_p = WAVE / seg_p, nslots_p = nwaves * spw_p;
@@ -157,7 +157,7 @@ __device__ __forceinline__ void newton_path(const md_path &p, int iters, const i
     // QR of A_0 (the k = 0 block of A) on member 0, then W = R^{-1}
     // (Q^H)_{0:n}, columns over all members
     if (member == 0) {
-      qr_wg<M, 2>(qsh, N, n, seg_q, A, long(L) * N * n, QR, vd, beta, st);
+      qr_wg<M, 4>(qsh, N, n, seg_q, A, long(L) * N * n, QR, vd, beta, st);
       inv_diag_range<M>(tid, nt, N, n, QR, invd, st);
     }
     gsync();

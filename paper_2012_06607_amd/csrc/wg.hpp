@@ -83,7 +83,9 @@ struct QrShared {
 // lis + r*seg): the segment tree of |a_i|^2 over i >= j, alpha from the lane
 // that holds row j; lane 0 of the wave stores the scalars when `keep` (all
 // lanes of the wave call this).
-template <int M, int RPL>
+// With HOLD false the column is read from QR (rows j.. as stored) instead of
+// `col`.
+template <int M, int RPL, bool HOLD = true>
 __device__ __forceinline__ void qr_reflector(const mdc<M> (&col)[RPL], int j, int N, int n, int seg,
                                              bool keep, QrShared<M> &sh, double *__restrict__ QR,
                                              long E, double *__restrict__ vdiag,
@@ -93,15 +95,24 @@ __device__ __forceinline__ void qr_reflector(const mdc<M> (&col)[RPL], int j, in
   mdr<M> s = md_zero<M>();
   mdc<M> alpha = c_zero<M>();
   bool first = true;
-#pragma unroll
-  for (int r = 0; r < RPL; ++r) {
-    const int i = lis + r * seg;
+  auto row = [&](int i, const mdc<M> &cv) __attribute__((always_inline)) {
     if (i >= j && i < N) {
-      const mdr<M> t = c_abs2<M>(col[r]);
+      const mdr<M> t = c_abs2<M>(cv);
       s = first ? t : md_add<M>(s, t);
       first = false;
+      if (i == j) alpha = cv;
     }
-    if (i == j) alpha = col[r];
+  };
+  if constexpr (HOLD) {
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) row(lis + r * seg, col[r]);
+  } else {
+    // rows read from QR, one at a time
+#pragma unroll 1
+    for (int r = 0; r < RPL; ++r) {
+      const int i = lis + r * seg;
+      if (i >= j && i < N) row(i, cload<M>(QR, E, long(i) * n + j));
+    }
   }
   s = seg_reduce_r<M>(s, seg);
   // The wave's first segment holds the column: its sums and alpha go to every
@@ -158,14 +169,46 @@ __device__ __forceinline__ void qr_reflector(const mdc<M> (&col)[RPL], int j, in
 
 // a_l -= beta (v^H a_l) v over rows i >= j by one segment; `anew` receives
 // the updated values (zero outside rows j..N-1).  The diagonal entry of
-// column j+1 is not stored: its reflector's R_jj replaces it.
-template <int M, int RPL>
+// column j+1 is not stored: its reflector's R_jj replaces it.  With HOLD
+// false nothing is held across the two passes: the reflector rows (v_j = v0,
+// the stored tail below) and the column are read where used (twice, through
+// L1), every updated entry is stored (the next reflector reads its column
+// back; its R_jj then replaces the diagonal) and `anew` is not written.
+template <int M, int RPL, bool HOLD = true>
 __device__ __forceinline__ void qr_update_column(bool live, int l, int j, int N, int n, int seg,
-                                                 const mdc<M> (&vi)[RPL], const mdr<M> &bet,
-                                                 double *__restrict__ QR, long E,
-                                                 mdc<M> (&anew)[RPL]) {
+                                                 const mdc<M> (&vi)[RPL], const mdc<M> &v0,
+                                                 const mdr<M> &bet, double *__restrict__ QR,
+                                                 long E, mdc<M> (&anew)[RPL]) {
   const int lane = lane_id();
   const int lis = lane & (seg - 1);
+  if constexpr (!HOLD) {
+    // one row at a time (the loops stay loops, so one row's values are live)
+    auto vrow = [&](int i) __attribute__((always_inline)) {
+      return i == j ? v0 : cload<M>(QR, E, long(i) * n + j);
+    };
+    mdc<M> w = c_zero<M>();
+    bool first = true;
+#pragma unroll 1
+    for (int r = 0; r < RPL; ++r) {
+      const int i = lis + r * seg;
+      if (live && i >= j && i < N) {
+        const mdc<M> t = c_mul<M>(c_conj<M>(vrow(i)), cload<M>(QR, E, long(i) * n + l));
+        w = first ? t : c_add<M>(w, t);
+        first = false;
+      }
+    }
+    w = seg_reduce_c<M>(w, seg);
+    w = shfl_c<M>(w, lane & ~(seg - 1));
+    const mdc<M> bw = c_mulr<M>(w, bet);
+#pragma unroll 1
+    for (int r = 0; r < RPL; ++r) {
+      const int i = lis + r * seg;
+      if (live && i >= j && i < N)
+        cstore<M>(QR, E, long(i) * n + l,
+                  c_sub<M>(cload<M>(QR, E, long(i) * n + l), c_mul<M>(bw, vrow(i))));
+    }
+    return;
+  }
   mdc<M> al[RPL];
   mdc<M> w = c_zero<M>();
   bool first = true;
@@ -211,17 +254,23 @@ __device__ __forceinline__ void qr_wg(QrShared<M> &sh, int N, int n, int seg, co
   __syncthreads();
   // step j = -1 only loads column 0 and forms reflector 0
   for (int j = -1; j < n; ++j) {
+    // with four or more rows per lane nothing is held across the rounds:
+    // the reflector and column rows are read where they are used
+    constexpr bool HOLD = RPL < 4;
     mdc<M> vi[RPL], anew[RPL];
+    mdc<M> v0 = c_zero<M>();
     mdr<M> bet = md_zero<M>();
     if (j >= 0) {
-      const mdc<M> v0 = sh.v0[j & 1];
+      v0 = sh.v0[j & 1];
       bet = sh.beta[j & 1];
+      if constexpr (HOLD) {
 #pragma unroll
-      for (int r = 0; r < RPL; ++r) {
-        const int i = lis + r * seg;
-        vi[r] = c_zero<M>();
-        if (i == j) vi[r] = v0;
-        else if (i > j && i < N) vi[r] = cload<M>(QR, E, long(i) * n + j);
+        for (int r = 0; r < RPL; ++r) {
+          const int i = lis + r * seg;
+          vi[r] = c_zero<M>();
+          if (i == j) vi[r] = v0;
+          else if (i > j && i < N) vi[r] = cload<M>(QR, E, long(i) * n + j);
+        }
       }
     }
     // Columns j+1.. go out round by round, one per slot.  Wave 0's first
@@ -250,16 +299,18 @@ __device__ __forceinline__ void qr_wg(QrShared<M> &sh, int N, int n, int seg, co
       const int l = k < k0 ? j + 1 + k * nslots + slot
                            : j + 1 + k0 * nslots + (k - k0) * others + (slot - spw);
       if (j < 0) {
+        if constexpr (HOLD) {
 #pragma unroll
-        for (int r = 0; r < RPL; ++r) {
-          const int i = lis + r * seg;
-          anew[r] = (l < n && i < N) ? cload<M>(QR, E, long(i) * n + l) : c_zero<M>();
+          for (int r = 0; r < RPL; ++r) {
+            const int i = lis + r * seg;
+            anew[r] = (l < n && i < N) ? cload<M>(QR, E, long(i) * n + l) : c_zero<M>();
+          }
         }
       } else {
-        qr_update_column<M, RPL>(l < n, l, j, N, n, seg, vi, bet, QR, E, anew);
+        qr_update_column<M, RPL, HOLD>(l < n, l, j, N, n, seg, vi, v0, bet, QR, E, anew);
       }
       if (k == 0 && wave == 0 && j + 1 < n)
-        qr_reflector<M, RPL>(anew, j + 1, N, n, seg, true, sh, QR, E, vdiag, beta, st);
+        qr_reflector<M, RPL, HOLD>(anew, j + 1, N, n, seg, true, sh, QR, E, vdiag, beta, st);
     }
     __syncthreads();
   }
