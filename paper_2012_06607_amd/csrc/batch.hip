@@ -125,14 +125,22 @@ __device__ __forceinline__ void newton_path(const md_path &p, int iters, const i
   a.f = f;
   a.A = A;
   const int seg_q = pow2_at_least((N + 3) / 4);  // QR: four rows per lane
-  const int seg_dx = dot_seg_throughput(N), seg_up = dot_seg_throughput(n);
+  // stage products: up to eight products per lane, or wider segments (fewer
+  // products per lane, a deeper tree) while all rows still fit in 256 lanes.
+  // The choice depends on the path's sizes only, so the bits do not depend
+  // on the launch shape or the gang split.
+  auto stage_seg = [&](int len, long rows) {
+    int sg = dot_seg_throughput(len);
+    const int smax = len >= WAVE ? WAVE : pow2_at_least(len);
+    while (sg < smax && rows * 2 * sg <= 4 * WAVE) sg *= 2;
+    return sg;
+  };
+  const int seg_dx = stage_seg(N, n);
   const int seg_p = pow2_at_least((N + 3) / 4);  // R^{-1} Q^H: four rows per lane
   const int spw_p = WAVE / seg_p, nslots_p = nwaves * spw_p;
   const int slot_p = wave * spw_p + lane_id() / seg_p;
   const int spw_x = WAVE / seg_dx, nslots_x = nwaves * spw_x;
   const int slot_x = wave * spw_x + lane_id() / seg_dx;
-  const int spw_u = WAVE / seg_up, nslots_u = nwaves * spw_u;
-  const int slot_u = wave * spw_u + lane_id() / seg_up;
   const int rgrp = eval_group(d);
   const int per_wave = term_lds_series(p.max_deg) * L;
   mdc<M> *lds = reinterpret_cast<mdc<M> *>(lds_raw);
@@ -176,6 +184,9 @@ __device__ __forceinline__ void newton_path(const md_path &p, int iters, const i
       __syncthreads();
       if (k < d) {
         const long rows = long(d - k) * N;
+        const int seg_up = stage_seg(n, rows);
+        const int spw_u = WAVE / seg_up, nslots_u = nwaves * spw_u;
+        const int slot_u = wave * spw_u + lane_id() / seg_up;
         for (long base = long(member) * nslots_u; base < rows; base += long(G) * nslots_u) {
           const long row = base + slot_u;
           stage_update_row<M>(row < rows, row, k, N, n, d, seg_up, A, dx, r);
