@@ -124,7 +124,6 @@ __device__ __forceinline__ void newton_path(const md_path &p, int iters, const i
   a.Ews = a.lay.E;
   a.f = f;
   a.A = A;
-  const int seg_q = pow2_at_least((N + 3) / 4);  // QR: four rows per lane
   // stage products: up to eight products per lane, or wider segments (fewer
   // products per lane, a deeper tree) while all rows still fit in 256 lanes.
   // The choice depends on the path's sizes only, so the bits do not depend
@@ -136,7 +135,15 @@ __device__ __forceinline__ void newton_path(const md_path &p, int iters, const i
     return sg;
   };
   const int seg_dx = stage_seg(N, n);
-  const int seg_p = pow2_at_least((N + 3) / 4);  // R^{-1} Q^H: four rows per lane
+  // QR and R^{-1} Q^H: up to four rows per lane, wider segments (fewer rows
+  // per lane) while all columns fit in 512 lanes; sizes only, as above
+  auto col_seg = [&](int cols) {
+    int sg = pow2_at_least((N + 3) / 4);
+    const int smax = N >= WAVE ? WAVE : pow2_at_least(N);
+    while (sg < smax && long(cols) * 2 * sg <= 8 * WAVE) sg *= 2;
+    return sg;
+  };
+  const int seg_q = col_seg(n), seg_p = col_seg(N);
   const int spw_p = WAVE / seg_p, nslots_p = nwaves * spw_p;
   const int slot_p = wave * spw_p + lane_id() / seg_p;
   const int spw_x = WAVE / seg_dx, nslots_x = nwaves * spw_x;
