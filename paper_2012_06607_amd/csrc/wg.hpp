@@ -560,19 +560,19 @@ __device__ __forceinline__ mdc<M> conv_part(const mdc<M> *X, int dx, const mdc<M
 }
 
 // z = X Y (deg X <= dx) truncated at d for the coefficient pairs (k, d-k)
-// of this lane's group; the group's partial sums go through a fixed-order
-// tree; results (times `mult`) to LDS Z or to workspace planes.  When X has
-// fewer coefficients than a group has lanes, each lane takes whole
-// coefficients instead.  Called by all 64 lanes of a wave.
+// of this lane's group, by the `nb` lanes of a block (`bl` is the lane's
+// index in it); the group's partial sums go through a fixed-order tree;
+// results (times `mult`) to LDS Z or to workspace planes.  When X has fewer
+// coefficients than a group has lanes, each lane takes whole coefficients
+// instead.  All lanes of the wave call this (the trees shuffle across it).
 template <int M>
-__device__ __forceinline__ void conv_group(const mdc<M> *X, int dx, const mdc<M> *Y, mdc<M> *Z,
-                                           int d, int r, double *ws, long Ews, long wbase,
-                                           int mult) {
-  const int lane = lane_id();
+__device__ __forceinline__ void conv_block(int bl, int nb, const mdc<M> *X, int dx, const mdc<M> *Y,
+                                           mdc<M> *Z, int d, int r, double *ws, long Ews,
+                                           long wbase, int mult) {
   if (dx < r) {
     // a short X (a coefficient series): one coefficient per lane, its few
     // products added in sequence
-    for (int k = lane; k <= d; k += WAVE) {
+    for (int k = bl; k <= d; k += nb) {
       mdc<M> z = conv_part<M>(X, dx, Y, k, 0, 1);
       if (mult > 1) {
         z.re = md_muld<M>(z.re, double(mult));
@@ -583,9 +583,9 @@ __device__ __forceinline__ void conv_group(const mdc<M> *X, int dx, const mdc<M>
     }
     return;
   }
-  const int pg = lane / r;
-  const int sub = lane - pg * r;
-  const int npg = WAVE / r;
+  const int pg = bl / r;
+  const int sub = bl - pg * r;
+  const int npg = nb / r;
   const int P = (d + 2) / 2;
   for (int base = 0; base < P; base += npg) {
     const int p = base + pg;
@@ -605,6 +605,40 @@ __device__ __forceinline__ void conv_group(const mdc<M> *X, int dx, const mdc<M>
       }
     }
   }
+}
+
+// One series product by the whole wave (groups of r lanes per pair).
+template <int M>
+__device__ __forceinline__ void conv_group(const mdc<M> *X, int dx, const mdc<M> *Y, mdc<M> *Z,
+                                           int d, int r, double *ws, long Ews, long wbase,
+                                           int mult) {
+  conv_block<M>(lane_id(), WAVE, X, dx, Y, Z, d, r, ws, Ews, wbase, mult);
+}
+
+// Lanes per coefficient pair when two full products share the wave (32
+// lanes each), or 0 when they should go one after the other: pairing pays
+// while the pairs of one product fit in half a wave (d <= 31).
+__host__ __device__ inline int eval_group2(int d) {
+  const int P = (d + 2) / 2;
+  return P <= WAVE / 2 ? (WAVE / 2) / P : 0;
+}
+
+// Two independent full products (deg X = d) into LDS: the first by lanes
+// 0..31, the second by lanes 32..63, r2 = eval_group2(d) lanes per pair; or
+// one after the other when r2 is 0.
+template <int M>
+__device__ __forceinline__ void conv_pair(const mdc<M> *X0, const mdc<M> *Y0, mdc<M> *Z0,
+                                          const mdc<M> *X1, const mdc<M> *Y1, mdc<M> *Z1, int d,
+                                          int r, int r2) {
+  if (r2 == 0) {
+    conv_block<M>(lane_id(), WAVE, X0, d, Y0, Z0, d, r, nullptr, 0, 0, 1);
+    conv_block<M>(lane_id(), WAVE, X1, d, Y1, Z1, d, r, nullptr, 0, 0, 1);
+    return;
+  }
+  const int lane = lane_id();
+  const bool hi = lane >= WAVE / 2;
+  conv_block<M>(lane & (WAVE / 2 - 1), WAVE / 2, hi ? X1 : X0, d, hi ? Y1 : Y0, hi ? Z1 : Z0, d,
+                r2, nullptr, 0, 0, 1);
 }
 
 // One term by one wave with its series in `lds` (term_lds_series(Dmax) x
@@ -696,15 +730,38 @@ __device__ __forceinline__ void eval_term_wave(const EvalArgs &a, int tau, int r
     coef_products();
     return;
   }
+  // forward P_{st+1} = P_st x_st and backward Q_j = x_{j-1} Q_{j+1} side by
+  // side; the last forward product goes with the first cross product
+  // C_j = P_{j-1} Q_{j+1} (all of whose inputs are ready by then), and the
+  // other cross products go two by two
+  const int r2 = eval_group2(d);
+  auto cross_next = [&](int j) {
+    while (j <= D - 1 && v[j - 1] == v[j - 2]) ++j;
+    return j;
+  };
+  int jc = cross_next(2);
   for (int st = 1; st <= D - 1; ++st) {
-    conv_group<M>(Pj(st), d, S(T.xs(st)), S(T.P(st + 1)), d, r, nullptr, 0, 0, 1);
     const int j = D - st;
-    if (j >= 2) conv_group<M>(S(T.xs(j - 1)), d, Qj(j + 1), S(T.Q(j)), d, r, nullptr, 0, 0, 1);
+    if (j >= 2) {
+      conv_pair<M>(Pj(st), S(T.xs(st)), S(T.P(st + 1)), S(T.xs(j - 1)), Qj(j + 1), S(T.Q(j)), d, r, r2);
+    } else if (jc <= D - 1) {
+      conv_pair<M>(Pj(st), S(T.xs(st)), S(T.P(st + 1)), Pj(jc - 1), Qj(jc + 1), S(T.C(jc)), d, r, r2);
+      jc = cross_next(jc + 1);
+    } else {
+      conv_group<M>(Pj(st), d, S(T.xs(st)), S(T.P(st + 1)), d, r, nullptr, 0, 0, 1);
+    }
     wave_sync();
   }
-  for (int j = 2; j <= D - 1; ++j)
-    if (v[j - 1] != v[j - 2])
-      conv_group<M>(Pj(j - 1), d, Qj(j + 1), S(T.C(j)), d, r, nullptr, 0, 0, 1);
+  while (jc <= D - 1) {
+    const int jn = cross_next(jc + 1);
+    if (jn <= D - 1) {
+      conv_pair<M>(Pj(jc - 1), Qj(jc + 1), S(T.C(jc)), Pj(jn - 1), Qj(jn + 1), S(T.C(jn)), d, r, r2);
+      jc = cross_next(jn + 1);
+    } else {
+      conv_group<M>(Pj(jc - 1), d, Qj(jc + 1), S(T.C(jc)), d, r, nullptr, 0, 0, 1);
+      jc = jn;
+    }
+  }
   if (a.mono)
     for (int k = lane; k < L; k += WAVE) cstore<M>(a.mono, Em, long(tau) * L + k, Pj(D)[k]);
   wave_sync();
