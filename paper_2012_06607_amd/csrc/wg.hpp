@@ -617,10 +617,10 @@ __device__ __forceinline__ void conv_group(const mdc<M> *X, int dx, const mdc<M>
 
 // Lanes per coefficient pair when two full products share the wave (32
 // lanes each), or 0 when they should go one after the other: pairing pays
-// while the pairs of one product fit in half a wave (d <= 31).
+// while each pair still gets two lanes of the half wave (d <= 31).
 __host__ __device__ inline int eval_group2(int d) {
   const int P = (d + 2) / 2;
-  return P <= WAVE / 2 ? (WAVE / 2) / P : 0;
+  return 2 * P <= WAVE / 2 ? (WAVE / 2) / P : 0;
 }
 
 // Two independent full products (deg X = d) into LDS: the first by lanes
