@@ -33,7 +33,7 @@ __device__ __forceinline__ void wave_sync() {
 // max over the workgroup of an exact selection (values are compared, the
 // bits of the largest are kept), through LDS
 template <int M>
-__device__ mdr<M> wg_max(mdr<M> v, mdr<M> *sh) {
+__device__ __forceinline__ mdr<M> wg_max(mdr<M> v, mdr<M> *sh) {
   for (int o = WAVE / 2; o > 0; o >>= 1) {
     const mdr<M> t = shfl_down_r<M>(v, o);
     if (lane_id() < o && md_less<M>(v, t)) v = t;
@@ -90,6 +90,7 @@ __device__ __forceinline__ void newton_path(const md_path &p, int iters, const i
                             int eval_waves, int member, int G, int32_t *gang_ctr) {
   __shared__ QrShared<M> qsh;
   __shared__ mdr<M> msh[16];  // one per wave, up to 1024 threads
+  __shared__ int term_next;   // the workgroup's term queue (one workgroup per path)
   const int N = p.N, n = p.n, d = p.d, L = d + 1;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int wave = tid / WAVE, nwaves = nt / WAVE;
@@ -157,15 +158,27 @@ __device__ __forceinline__ void newton_path(const md_path &p, int iters, const i
     if (G > 1) gang_barrier(gang_ctr, G, round, st);
     else __syncthreads();
   };
+  if (tid == 0) term_next = 0;
+  __syncthreads();
   for (int it = 0; it < iters; ++it) {
-    // evaluation and differentiation: waves (of all members) over terms,
-    // then the sums, one (equation, coefficient) pair per lane (each wave
-    // clears its rows of A first), with r = -f written by the lane that
-    // formed f
-    if (wave < eval_waves)
-      for (int tau = member * eval_waves + wave; tau < p.M; tau += G * eval_waves)
+    // evaluation and differentiation: waves over terms (a path on one
+    // workgroup: each wave takes the next term from the workgroup's queue,
+    // so terms of unequal degree even out; a gang: members and waves take
+    // terms round robin), then the sums, one (equation, coefficient) pair
+    // per lane (each wave clears its rows of A first), with r = -f written
+    // by the lane that formed f
+    if (wave < eval_waves) {
+      auto next_term = [&](int prev) __attribute__((always_inline)) {
+        if (G > 1) return prev < 0 ? member * eval_waves + wave : prev + G * eval_waves;
+        int t = 0;
+        if (lane_id() == 0) t = atomicAdd(&term_next, 1);
+        return __shfl(t, 0);
+      };
+      for (int tau = next_term(-1); tau < p.M; tau = next_term(tau))
         eval_term_wave<M>(a, tau, rgrp, lds + wave * per_wave, [] { wave_sync(); });
+    }
     gsync();
+    if (tid == 0) term_next = 0;  // for the next step (read after later barriers)
     for (long g0 = long(member) * nt + wave * WAVE; g0 < long(L) * N; g0 += long(G) * nt)
       eval_accumulate_wave<M>(a, g0, r, [] { wave_sync(); });
     gsync();

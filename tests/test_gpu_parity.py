@@ -235,6 +235,20 @@ def test_qr_within_tolerance(B, m, shape):
     compare_qr((host(QR), host(vd), host(beta)), (QRw, vdw, bw), m, s[0] / s[-1])
 
 
+@pytest.mark.parametrize("m", (2, 4))
+def test_qr_tall_four_rows_per_lane(B, m):
+    """N above 128 takes four rows per lane in md_qr, the form that reads
+    the reflector and column rows where they are used instead of holding
+    them (the batched kernel's QR form)."""
+    N, n = 140, 60
+    A0 = I.unit_complex(I.rng(958, m, N, n), m, N, n)
+    QRw, vdw, bw, stw = oracle.qr(A0)
+    QR, vd, beta, st = B.md_qr(dev(A0))
+    assert int(host(st)[0]) == stw == 0
+    s = np.linalg.svd(A0[0, 0] + 1j * A0[1, 0], compute_uv=False)
+    compare_qr((host(QR), host(vd), host(beta)), (QRw, vdw, bw), m, s[0] / s[-1])
+
+
 def test_qr_flags_singular_column(B):
     m = 2
     A0 = I.unit_complex(I.rng(957), m, 5, 5)
