@@ -107,6 +107,7 @@ __device__ __forceinline__ void newton_path(const md_path &p, int iters, const i
   double *W = reinterpret_cast<double *>(w + lay.off_solve + sl.off_G);
   double *invd = W + size_t(2) * M * n * N;
   double *x = reals + p.x;
+  int32_t *gang_terms = reinterpret_cast<int32_t *>(w + lay.off_ctr);
   EvalArgs a;
   a.d = d;
   a.N = N;
@@ -159,26 +160,33 @@ __device__ __forceinline__ void newton_path(const md_path &p, int iters, const i
     else __syncthreads();
   };
   if (tid == 0) term_next = 0;
-  __syncthreads();
+  if (G > 1) {
+    if (member == 0 && tid == 0) *gang_terms = 0;
+    gsync();  // the gang's term queue starts at zero for every member
+  } else {
+    __syncthreads();
+  }
   for (int it = 0; it < iters; ++it) {
-    // evaluation and differentiation: waves over terms (a path on one
-    // workgroup: each wave takes the next term from the workgroup's queue,
-    // so terms of unequal degree even out; a gang: members and waves take
-    // terms round robin), then the sums, one (equation, coefficient) pair
-    // per lane (each wave clears its rows of A first), with r = -f written
-    // by the lane that formed f
+    // evaluation and differentiation: waves over terms, each wave taking
+    // the next term from a queue (in LDS for a path on one workgroup, in the
+    // path's workspace for a gang), so terms of unequal degree even out;
+    // then the sums, one (equation, coefficient) pair per lane (each wave
+    // clears its rows of A first), with r = -f written by the lane that
+    // formed f
     if (wave < eval_waves) {
-      auto next_term = [&](int prev) __attribute__((always_inline)) {
-        if (G > 1) return prev < 0 ? member * eval_waves + wave : prev + G * eval_waves;
+      auto next_term = [&](int) __attribute__((always_inline)) {
         int t = 0;
-        if (lane_id() == 0) t = atomicAdd(&term_next, 1);
+        if (lane_id() == 0) t = G > 1 ? atomicAdd(gang_terms, 1) : atomicAdd(&term_next, 1);
         return __shfl(t, 0);
       };
       for (int tau = next_term(-1); tau < p.M; tau = next_term(tau))
         eval_term_wave<M>(a, tau, rgrp, lds + wave * per_wave, [] { wave_sync(); });
     }
     gsync();
-    if (tid == 0) term_next = 0;  // for the next step (read after later barriers)
+    // the queues start again at zero for the next step (read after later
+    // barriers, gang barriers for the gang's queue)
+    if (tid == 0) term_next = 0;
+    if (G > 1 && member == 0 && tid == 0) *gang_terms = 0;
     for (long g0 = long(member) * nt + wave * WAVE; g0 < long(L) * N; g0 += long(G) * nt)
       eval_accumulate_wave<M>(a, g0, r, [] { wave_sync(); });
     gsync();

@@ -46,7 +46,7 @@ struct SolveLayout {
 
 // Newton step: f, A, QR factors, dx, then the solve and eval workspaces.
 struct NewtonLayout {
-  size_t off_f, off_A, off_QR, off_vd, off_beta, off_dx, off_solve, off_eval, bytes;
+  size_t off_f, off_A, off_QR, off_vd, off_beta, off_dx, off_solve, off_eval, off_ctr, bytes;
   __host__ __device__ NewtonLayout(int m, int N, int n, int d, int M, int max_deg) {
     const size_t L = size_t(d + 1);
     size_t o = 0;
@@ -66,6 +66,8 @@ struct NewtonLayout {
     o += SolveLayout(m, N, n, d).bytes;
     off_eval = o;
     o += EvalLayout(m, N, n, d, M, max_deg).bytes;
+    off_ctr = o;  // the term queue of a gang of workgroups (batched launch)
+    o += 256;
     bytes = o;
   }
 };
