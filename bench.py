@@ -45,12 +45,12 @@ M1, N1, D1 = 4, 32, 16    # the single-path step
 TRAFFIC = {
     "k_newton_batch": {"fetch_kib": 74982748.2, "fetch_scale": 262144 / 131092.6875,
                        "write_kib": 31708423.4, "write_scale": 262144 / 262149.75,
-                       "sha256": "f9beb5b364dd8dfd16d460aac32be8dc6b8b047f498e59d2a078dc0c0eee338f",
+                       "sha256": "644da317178a59c4f7325b4840c50ac20a6ca2db60c6f0c0993942d748fca7ef",
                        "sources": ("batch.hip", "internal.hpp", "common.hpp", "md.hpp", "wg.hpp",
                                    "layout.hpp", "series.hpp")},
     "k_qr": {"fetch_kib": 102.375, "fetch_scale": 262144 / 131092.6875, "write_kib": 67.0,
              "write_scale": 262144 / 262149.75,
-             "sha256": "65efe9c109b9fb641d43d73e5ea94b7a5ca450d2688132d8524cc1e2134c00f5",
+             "sha256": "d2495080120ca891c2bed1dd60eb52bc12e915974f8f5e5a216da1488b05e47c",
              "sources": ("qr.hip", "internal.hpp", "common.hpp", "md.hpp", "wg.hpp",
                          "layout.hpp", "series.hpp")},
 }

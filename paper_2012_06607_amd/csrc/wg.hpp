@@ -607,12 +607,30 @@ __device__ __forceinline__ void conv_block(int bl, int nb, const mdc<M> *X, int 
   }
 }
 
+// conv_block as one shared function for five or more limbs: a copy inlined
+// at every call site makes those kernels very large (and slow to compile)
+// for no measured gain.  A leaf without LDS variables of its own.
+template <int M>
+__device__ __noinline__ void conv_block_call(int bl, int nb, const mdc<M> *X, int dx,
+                                             const mdc<M> *Y, mdc<M> *Z, int d, int r, double *ws,
+                                             long Ews, long wbase, int mult) {
+  conv_block<M>(bl, nb, X, dx, Y, Z, d, r, ws, Ews, wbase, mult);
+}
+
+template <int M>
+__device__ __forceinline__ void conv_any(int bl, int nb, const mdc<M> *X, int dx, const mdc<M> *Y,
+                                         mdc<M> *Z, int d, int r, double *ws, long Ews, long wbase,
+                                         int mult) {
+  if constexpr (M >= 5) conv_block_call<M>(bl, nb, X, dx, Y, Z, d, r, ws, Ews, wbase, mult);
+  else conv_block<M>(bl, nb, X, dx, Y, Z, d, r, ws, Ews, wbase, mult);
+}
+
 // One series product by the whole wave (groups of r lanes per pair).
 template <int M>
 __device__ __forceinline__ void conv_group(const mdc<M> *X, int dx, const mdc<M> *Y, mdc<M> *Z,
                                            int d, int r, double *ws, long Ews, long wbase,
                                            int mult) {
-  conv_block<M>(lane_id(), WAVE, X, dx, Y, Z, d, r, ws, Ews, wbase, mult);
+  conv_any<M>(lane_id(), WAVE, X, dx, Y, Z, d, r, ws, Ews, wbase, mult);
 }
 
 // Lanes per coefficient pair when two full products share the wave (32
@@ -625,20 +643,22 @@ __host__ __device__ inline int eval_group2(int d) {
 
 // Two independent full products (deg X = d) into LDS: the first by lanes
 // 0..31, the second by lanes 32..63, r2 = eval_group2(d) lanes per pair; or
-// one after the other when r2 is 0.
+// one after the other when r2 is 0, and always for five or more limbs.
 template <int M>
 __device__ __forceinline__ void conv_pair(const mdc<M> *X0, const mdc<M> *Y0, mdc<M> *Z0,
                                           const mdc<M> *X1, const mdc<M> *Y1, mdc<M> *Z1, int d,
                                           int r, int r2) {
-  if (r2 == 0) {
-    conv_block<M>(lane_id(), WAVE, X0, d, Y0, Z0, d, r, nullptr, 0, 0, 1);
-    conv_block<M>(lane_id(), WAVE, X1, d, Y1, Z1, d, r, nullptr, 0, 0, 1);
+  if (M >= 5 || r2 == 0) {
+    conv_any<M>(lane_id(), WAVE, X0, d, Y0, Z0, d, r, nullptr, 0, 0, 1);
+    conv_any<M>(lane_id(), WAVE, X1, d, Y1, Z1, d, r, nullptr, 0, 0, 1);
     return;
   }
-  const int lane = lane_id();
-  const bool hi = lane >= WAVE / 2;
-  conv_block<M>(lane & (WAVE / 2 - 1), WAVE / 2, hi ? X1 : X0, d, hi ? Y1 : Y0, hi ? Z1 : Z0, d,
-                r2, nullptr, 0, 0, 1);
+  if constexpr (M < 5) {
+    const int lane = lane_id();
+    const bool hi = lane >= WAVE / 2;
+    conv_block<M>(lane & (WAVE / 2 - 1), WAVE / 2, hi ? X1 : X0, d, hi ? Y1 : Y0, hi ? Z1 : Z0,
+                  d, r2, nullptr, 0, 0, 1);
+  }
 }
 
 // One term by one wave with its series in `lds` (term_lds_series(Dmax) x
