@@ -850,10 +850,13 @@ __device__ __forceinline__ void eval_accumulate_row(const EvalArgs &a, int i, in
   cstore<M>(a.f, long(L) * a.N, long(k) * a.N + i, acc);
 }
 
-// Rows g0 .. g0+63 of the Jacobian sums (row g = k N + i) by one wave: the
-// wave clears the rows' A entries together (consecutive lanes, consecutive
-// addresses), then each lane forms its row as eval_accumulate_row and
-// writes r_k[i] = -f_k[i].  All lanes of the wave call this.
+// Rows g0 .. g0+63 of the Jacobian sums by one wave, row g being
+// coefficient k = g mod (d+1) of equation i = g / (d+1) (consecutive lanes
+// take consecutive coefficients of one equation, so their reads of a term's
+// slots are consecutive words): the wave clears the rows' A entries
+// together (lanes over the entries of a row), then each lane forms its row
+// as eval_accumulate_row and writes r_k[i] = -f_k[i].  All lanes of the wave
+// call this.
 template <int M, class Sync>
 __device__ __forceinline__ void eval_accumulate_wave(const EvalArgs &a, long g0, double *__restrict__ r,
                                                      Sync wave_sync) {
@@ -862,13 +865,19 @@ __device__ __forceinline__ void eval_accumulate_wave(const EvalArgs &a, long g0,
   const long EA = rows * a.n, Er = rows;
   const int lane = lane_id();
   const long cnt = rows - g0 < WAVE ? rows - g0 : WAVE;
-  for (long e = lane; e < cnt * a.n; e += WAVE) cstore<M>(a.A, EA, g0 * a.n + e, c_zero<M>());
+  for (long e = lane; e < cnt * a.n; e += WAVE) {
+    const long g = g0 + e / a.n;
+    const int l = int(e - (g - g0) * a.n);
+    const int i = int(g / L), k = int(g - long(i) * L);
+    cstore<M>(a.A, EA, (long(k) * a.N + i) * a.n + l, c_zero<M>());
+  }
   wave_sync();
   const long g = g0 + lane;
   if (g < rows) {
-    const int i = int(g % a.N), k = int(g / a.N);
+    const int i = int(g / L), k = int(g - long(i) * L);
     eval_accumulate_row<M>(a, i, k, true);
-    cstore<M>(r, Er, g, c_neg<M>(cload<M>(a.f, Er, g)));
+    const long e = long(k) * a.N + i;
+    cstore<M>(r, Er, e, c_neg<M>(cload<M>(a.f, Er, e)));
   }
 }
 
