@@ -61,7 +61,9 @@ enum {
   MD_ST_NONFINITE = 2, /* an infinity or NaN reached a result */
   MD_ST_BADPATH = 4,   /* md_newton_batch: a path's sizes or precision are not supported */
   MD_ST_GANG = 8,      /* md_newton_batch: a gang barrier waited too long (results invalid) */
-  MD_ST_NOTRUN = 16    /* md_newton_batch: no workgroup took the path's jobs */
+  MD_ST_NOTRUN = 16,   /* md_newton_batch: no workgroup took the path's jobs */
+  MD_ST_DIVERGED = 32  /* the update to the last coefficient grew (md_newton_step), or a degree
+                          of the adaptive driver ended with it above the divergence bound */
 };
 
 /* Polynomial system f = (f_1..f_N) in x = (x_1..x_n), N >= n, whose terms
@@ -140,11 +142,17 @@ int md_series_solve(int m, int N, int n, int d, const double *QR, const double *
 /* One Newton step on truncated power series (Section 4): evaluate and
  * differentiate the system at x(t), b = -f, solve A(t) dx(t) = b(t) with one
  * QR of A_0 and the staggered substitution, then x(t) += dx(t).
- * x: in/out planes (2, m, d+1, n) with n = sys->n; dx_norm: real planes
- * (m, 2) (may be NULL): [max_i |dx_{d,i}|, max_{k,i} |dx_{k,i}|], the
- * modulus of the update to the last coefficient (Section 6) and the largest
- * update of any coefficient.  Workspace:
- * md_workspace_bytes(MD_FN_NEWTON, m, N, n, d, M, max_deg).
+ * x: in/out planes (2, m, d+1, n) with n = sys->n; dx_norm: in/out real
+ * planes (m, 2) (may be NULL).  On output it holds
+ * [max_i |dx_{d,i}|, max_{k,i} |dx_{k,i}|], the modulus of the update to the
+ * last coefficient (Section 6) and the largest update of any coefficient.
+ * On input its first entry is the previous step's |dx_d| (as an earlier
+ * call wrote it) or zero: when it is positive and this step's |dx_d| is
+ * larger, MD_ST_DIVERGED is set (the update grew from one step to the
+ * next).  Growth is expected while the t-adic convergence of the series
+ * still changes coefficient d (the first ceil(log2(d+1)) + 1 steps) and at
+ * the rounding floor; the caller judges the bit with that in mind.
+ * Workspace: md_workspace_bytes(MD_FN_NEWTON, m, N, n, d, M, max_deg).
  * Errors: as md_poly_eval_diff and md_series_solve. */
 int md_newton_step(int m, int d, const md_system *sys, double *x, double *dx_norm, void *ws,
                    size_t ws_bytes, int32_t *status, void *stream);
@@ -201,13 +209,19 @@ int md_norm2(int m, int64_t count, const double *x, double *out, void *stream);
  * Many independent solution paths in one persistent launch: the paper's job
  * queue (Section 5, Figure 1) with workgroups as workers and one device
  * atomic as the counter; a job is a whole path, `iters` Newton steps run by
- * one workgroup with barriers between the stages.  Every stage runs the
- * same segment-level code as md_newton_step, so a batched path gives the
- * same bits as md_newton_step applied `iters` times to that path.
+ * one workgroup (or a gang of workgroups) with barriers between the stages.
+ * The kernel sums its dot products in its own fixed order (more products
+ * per lane than md_newton_step), so a batched path agrees with
+ * md_newton_step applied `iters` times within the solve's rounding
+ * tolerance, not bit for bit; within the batched kernel the order depends
+ * only on the path's sizes, so every launch shape, job order, queue layout
+ * and gang split gives the same bits.
  *
  * One path, in a device array of md_path (all offsets are element offsets):
- *   m in 1..4 (the batched kernel carries double to quad double), N == n or
- *   N > n with N <= 64, d >= 0;
+ *   m in 1..4 (the batched kernel carries double to quad double),
+ *   1 <= n <= N <= 64, d >= 0 (md_newton_batch refuses a batch whose max_m
+ *   or max_N is outside these ranges; a path table that breaks them anyway
+ *   gets MD_ST_BADPATH for that path, which is then not run);
  *   eq_ptr, term_ptr, factors: offsets into `ints` (int32) of the path's
  *   system structure, laid out as in md_system (M terms, max_deg factors at
  *   most, coefficient degree dc);
@@ -242,19 +256,20 @@ size_t md_batch_lds_bytes(int max_m, int max_d, int max_deg, int eval_waves);
  * stream (so the call can be captured in a graph and replayed).  status:
  * device int32[npaths], MD_ST_* bits per path (cleared by the caller; the
  * call sets MD_ST_NOTRUN first and clears it when the path is done).
- * max_m, max_d, max_deg: maxima over the paths (host values, they size the
- * LDS); grid: the number of persistent workgroups (each queue needs as many
+ * max_m, max_N, max_d, max_deg: maxima over the paths (host values; max_m
+ * and max_N must be at most 4 and 64, and max_d, max_deg size the LDS);
+ * grid: the number of persistent workgroups (each queue needs as many
  * resident workgroups on its die as its largest gang); block: threads per
  * workgroup, 256 or 512; eval_waves (1..block/64): waves per workgroup that
  * evaluate terms; path_clock (may be NULL): device int64[2*npaths],
  * receives for every path the device wall clock (md_wall_clock_hz ticks per
  * second) when its member 0 took it and when it finished.
- * Errors: MD_EINVAL, MD_ENULL, MD_ESHAPE (LDS above md_device_lds_bytes()),
- * MD_EHIP. */
+ * Errors: MD_EINVAL (max_m outside 1..4 among others), MD_ENULL, MD_ESHAPE
+ * (max_N outside 1..64, or LDS above md_device_lds_bytes()), MD_EHIP. */
 int md_newton_batch(int npaths, const md_path *paths, int njobs, const int32_t *jobs, int nq,
                     const int32_t *qbegin, const int32_t *ints, double *reals, double *ws,
                     int iters, int32_t *counters, int32_t *gang_ctr, int32_t *status, int max_m,
-                    int max_d, int max_deg, int grid, int block, int eval_waves,
+                    int max_N, int max_d, int max_deg, int grid, int block, int eval_waves,
                     int64_t *path_clock, void *stream);
 
 /* Writes, for each of nblocks workgroups of a small launch, the accelerator

@@ -67,8 +67,8 @@
 
 enum { C_ADD, C_SUB, C_MUL, C_DIV, C_FMA, C_SQRT, C_MDADD, C_MDMUL, C_MDDIV,
        C_MDMULD, C_NCOUNT };
-static int64_t CNT[C_NCOUNT];
-static int depth; /* > 0 while inside a multiple-double division */
+static _Thread_local int64_t CNT[C_NCOUNT]; /* per thread: callers may run the oracle on several threads */
+static _Thread_local int depth; /* > 0 while inside a multiple-double division */
 
 void orc_reset_counters(void) { memset(CNT, 0, sizeof CNT); }
 void orc_get_counters(int64_t *out) { memcpy(out, CNT, sizeof CNT); }

@@ -51,8 +51,10 @@ class NewtonSolve(torch.autograd.Function):
 
 class SumAbs2(torch.autograd.Function):
     """L = sum of |z|^2 over the entries of md planes; forward returns the
-    leading double of L (from md_norm2), backward the md-valued 2 g z (every
-    limb scaled, exact when the upstream g is a power of two, such as 1)."""
+    leading double of L (from md_norm2), backward the md-valued 2 g z: the
+    real and imaginary planes each multiplied by the double 2 g in the
+    library (md_elementwise's md x double product, renormalised), so the
+    gradient keeps all m limbs for any upstream g."""
 
     @staticmethod
     def forward(ctx, z):
@@ -64,7 +66,16 @@ class SumAbs2(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         (z,) = ctx.saved_tensors
-        return 2.0 * g * z
+        m = z.shape[1]
+        zf = z.reshape(2, m, -1).contiguous()
+        count = zf.shape[2]
+        # the scale as the leading limb of an md operand (2 g is exact)
+        scale = torch.zeros((m, count), dtype=torch.float64, device=z.device)
+        scale[0] = (2.0 * g.to(torch.float64)).reshape(())
+        out = torch.empty_like(zf)
+        for part in range(2):
+            out[part] = B.md_elementwise("muld", zf[part].contiguous(), scale)
+        return out.reshape(z.shape)
 
 
 def newton_solve(coef: torch.Tensor, sysd: B.DeviceSystem, x0: torch.Tensor, iters: int,

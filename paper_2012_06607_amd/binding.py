@@ -20,7 +20,8 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libmdseries.so")
 
 MD_FN_EVAL, MD_FN_SOLVE, MD_FN_NEWTON, MD_FN_ADJOINT, MD_FN_ADJOINT_STORE = 1, 2, 3, 4, 5
-MD_ST_SINGULAR, MD_ST_NONFINITE = 1, 2
+MD_ST_SINGULAR, MD_ST_NONFINITE, MD_ST_BADPATH, MD_ST_GANG, MD_ST_NOTRUN = 1, 2, 4, 8, 16
+MD_ST_DIVERGED = 32
 OPS = {"add": 0, "sub": 1, "mul": 2, "div": 3, "sqrt": 4, "rsqrt": 5, "muld": 6,
        "cadd": 7, "csub": 8, "cmul": 9, "cdiv": 10, "cabs2": 11}
 REAL_OPS = ("add", "sub", "mul", "div", "sqrt", "rsqrt", "muld")
@@ -246,7 +247,8 @@ def md_newton_step(sysd: DeviceSystem, x: torch.Tensor, dx_norm=None, ws=None, s
     m = _limbs(x)
     _, _, L, n = x.shape
     if dx_norm is None:
-        dx_norm = torch.empty((m, 2), dtype=torch.float64, device=x.device)
+        # zero: no previous step to compare the update with (MD_ST_DIVERGED)
+        dx_norm = torch.zeros((m, 2), dtype=torch.float64, device=x.device)
     if ws is None:
         ws = workspace(MD_FN_NEWTON, m, sysd.N, n, L - 1, sysd.host.M, sysd.host.max_deg, x.device)
     if status is None:
@@ -329,6 +331,7 @@ MD_PATH_DTYPE = np.dtype([("m", "<i4"), ("N", "<i4"), ("n", "<i4"), ("d", "<i4")
                           ("eq_ptr", "<i8"), ("term_ptr", "<i8"), ("factors", "<i8"),
                           ("coef", "<i8"), ("x", "<i8"), ("dx_norm", "<i8"), ("ws", "<i8")])
 assert MD_PATH_DTYPE.itemsize == 88
+BATCH_MAX_M, BATCH_MAX_N = 4, 64
 
 
 class BatchedPaths:
@@ -351,6 +354,13 @@ class BatchedPaths:
             d = x.shape[2] - 1
             if x.shape != (2, m, d + 1, sysm.n):
                 raise MdError(f"path {p}: x must have shape (2, m, d+1, n)")
+            # the batched kernel carries double to quad double and at most 64
+            # equations (one lane per row of the QR and of R^{-1} Q^H segments)
+            if not 1 <= m <= BATCH_MAX_M:
+                raise MdError(f"path {p}: m={m} is not carried by the batched kernel (1..4)")
+            if not 1 <= sysm.n <= sysm.N <= BATCH_MAX_N:
+                raise MdError(f"path {p}: needs 1 <= n <= N <= {BATCH_MAX_N} "
+                              f"(n={sysm.n}, N={sysm.N})")
             t = table[p]
             t["m"], t["N"], t["n"], t["d"] = m, sysm.N, sysm.n, d
             t["M"], t["dc"], t["max_deg"] = sysm.M, sysm.dc, sysm.max_deg
@@ -376,6 +386,7 @@ class BatchedPaths:
         self.table = table
         self.cost = cost
         self.max_m = int(table["m"].max()) if len(paths) else 1
+        self.max_N = int(table["N"].max()) if len(paths) else 1
         self.max_d = int(table["d"].max()) if len(paths) else 0
         self.max_deg = int(table["max_deg"].max()) if len(paths) else 0
         self.paths_dev = torch.as_tensor(table.view(np.uint8).copy(), device=dev)
@@ -483,7 +494,7 @@ def md_newton_batch(batch: BatchedPaths, iters: int, grid: int | None = None,
     L = lib()
     P, i32 = ctypes.c_void_p, ctypes.c_int
     L.md_newton_batch.argtypes = [i32, P, i32, P, i32, P, P, P, P, i32, P, P, P, i32, i32, i32,
-                                  i32, i32, i32, P, P]
+                                  i32, i32, i32, i32, P, P]
     L.md_newton_batch.restype = ctypes.c_int
     if eval_waves is None:
         eval_waves = block // 64
@@ -503,8 +514,8 @@ def md_newton_batch(batch: BatchedPaths, iters: int, grid: int | None = None,
                              _ptr(batch.qbegin, torch.int32), _ptr(batch.ints, torch.int32),
                              _ptr(batch.reals), _ptr(batch.ws), iters,
                              _ptr(batch.counters, torch.int32), _ptr(batch.gang_ctr, torch.int32),
-                             _ptr(batch.status, torch.int32), batch.max_m, batch.max_d,
-                             batch.max_deg, grid, block, eval_waves,
+                             _ptr(batch.status, torch.int32), batch.max_m, batch.max_N,
+                             batch.max_d, batch.max_deg, grid, block, eval_waves,
                              _ptr(path_clock, torch.int64), _stream(stream)), "md_newton_batch")
     return batch
 

@@ -71,13 +71,29 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
-    """Compile every kernel source and link the shared library; returns its path."""
+def _stale(src: str, headers_mtime: float) -> bool:
+    obj = os.path.join(OBJ, os.path.basename(src)[:-4] + ".o")
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return t < os.path.getmtime(src) or t < headers_mtime
+
+
+def build(jobs: int | None = None, verbose: bool = False, changed_only: bool = False) -> str:
+    """Compile every kernel source and link the shared library; returns its
+    path.  changed_only: recompile only the sources newer than their object
+    (any header change recompiles everything)."""
     os.makedirs(OBJ, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
-    jobs = jobs or min(len(srcs), max(1, min(16, os.cpu_count() or 1)))
+    todo = srcs
+    if changed_only:
+        hdrs = glob.glob(os.path.join(CSRC, "*.hpp")) + glob.glob(os.path.join(ROOT, "include", "*.h"))
+        hm = max((os.path.getmtime(h) for h in hdrs), default=0.0)
+        todo = [s for s in srcs if _stale(s, hm)]
+    jobs = jobs or min(max(len(todo), 1), max(1, min(16, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        list(ex.map(_compile, todo))
+    objs = [os.path.join(OBJ, os.path.basename(s)[:-4] + ".o") for s in srcs]
     tmp = LIB + f".tmp{os.getpid()}"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -90,5 +106,5 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, changed_only="--changed" in sys.argv)
     sys.exit(0)

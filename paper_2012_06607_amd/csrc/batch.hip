@@ -284,11 +284,12 @@ __global__ void __launch_bounds__(BLOCK) k_newton_batch(int npaths, const md_pat
     if (job >= end) break;
     const int path = jobs[2 * job];
     const int G = jobs[2 * job + 1] >> 8, member = jobs[2 * job + 1] & 0xff;
+    if (path < 0 || path >= npaths) continue;
     const md_path p = paths[path];
-    const bool ok = path >= 0 && path < npaths && G >= 1 && member < G && p.N >= p.n &&
-                    p.n >= 1 && p.N <= WAVE && p.d >= 0 && p.max_deg >= 0;
+    const bool ok = G >= 1 && member < G && p.N >= p.n && p.n >= 1 && p.N <= WAVE &&
+                    p.d >= 0 && p.max_deg >= 0 && p.m >= 1 && p.m <= 4;
     if (!ok) {
-      if (threadIdx.x == 0 && path >= 0 && path < npaths) atomicOr(status + path, MD_ST_BADPATH);
+      if (threadIdx.x == 0) atomicOr(status + path, MD_ST_BADPATH);
       continue;
     }
     if (clk && threadIdx.x == 0 && member == 0) clk[2 * path] = wall_clock64();
@@ -323,13 +324,18 @@ extern "C" size_t md_batch_lds_bytes(int max_m, int max_d, int max_deg, int eval
 extern "C" int md_newton_batch(int npaths, const md_path *paths, int njobs, const int32_t *jobs,
                                int nq, const int32_t *qbegin, const int32_t *ints, double *reals,
                                double *ws, int iters, int32_t *counters, int32_t *gang_ctr,
-                               int32_t *status, int max_m, int max_d, int max_deg, int grid,
-                               int block, int eval_waves, int64_t *path_clock, void *stream) {
+                               int32_t *status, int max_m, int max_N, int max_d, int max_deg,
+                               int grid, int block, int eval_waves, int64_t *path_clock,
+                               void *stream) {
   if (npaths < 0 || njobs < 0 || iters < 0 || grid < 1 || (block != 256 && block != 512) ||
       eval_waves < 1 || eval_waves > block / WAVE || nq < 1 || nq > 64)
     return fail(MD_EINVAL,
                 "md_newton_batch: npaths=%d njobs=%d iters=%d grid=%d block=%d eval_waves=%d nq=%d",
                 npaths, njobs, iters, grid, block, eval_waves, nq);
+  if (max_m < 1 || max_m > 4)
+    return fail(MD_EINVAL, "md_newton_batch: max_m=%d must be in 1..4", max_m);
+  if (max_N < 1 || max_N > WAVE)
+    return fail(MD_ESHAPE, "md_newton_batch: max_N=%d must be in 1..%d", max_N, WAVE);
   if (npaths == 0) return MD_OK;
   if (!paths || !jobs || !qbegin || !ints || !reals || !ws || !counters || !gang_ctr || !status)
     return fail(MD_ENULL, "md_newton_batch: null pointer");

@@ -17,9 +17,11 @@ __global__ void __launch_bounds__(256) k_update(long E, const double *__restrict
 
 // max_i |dx_{d,i}| and max_{k,i} |dx_{k,i}| (maxima of |.|^2 are exact
 // selections, then one square root each), written as real planes (m, 2).
+// out[0] on entry is the previous step's |dx_d| (or zero): a larger one now
+// sets MD_ST_DIVERGED.
 template <int M>
 __global__ void __launch_bounds__(256) k_norms(int d, int n, const double *__restrict__ dx,
-                                               double *__restrict__ out) {
+                                               double *__restrict__ out, int32_t *status) {
   __shared__ mdr<M> sh_d[256], sh_a[256];
   const long E = long(d + 1) * n;
   const int t = threadIdx.x;
@@ -40,7 +42,10 @@ __global__ void __launch_bounds__(256) k_norms(int d, int n, const double *__res
     __syncthreads();
   }
   if (t == 0) {
-    rstore<M>(out, 2, 0, md_sqrt<M>(sh_d[0]));
+    const mdr<M> prev = rload<M>(out, 2, 0);
+    const mdr<M> nd = md_sqrt<M>(sh_d[0]);
+    if (status && prev.v[0] > 0.0 && md_less<M>(prev, nd)) atomicOr(status, MD_ST_DIVERGED);
+    rstore<M>(out, 2, 0, nd);
     rstore<M>(out, 2, 1, md_sqrt<M>(sh_a[0]));
   }
 }
@@ -82,7 +87,7 @@ extern "C" int md_newton_step(int m, int d, const md_system *sys, double *x, dou
     long blocks = (E + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     k_update<Mm><<<dim3(unsigned(blocks)), dim3(256), 0, s>>>(E, dx, x);
-    if (dx_norm) k_norms<Mm><<<dim3(1), dim3(256), 0, s>>>(d, n, dx, dx_norm);
+    if (dx_norm) k_norms<Mm><<<dim3(1), dim3(256), 0, s>>>(d, n, dx, dx_norm, status);
     return check_launch("md_newton_step (update)");
   });
 }

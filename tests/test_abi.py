@@ -113,18 +113,25 @@ def test_adjoint_host_checks(lib):
 def test_batch_host_checks(lib):
     P = ctypes.c_void_p
     i = ctypes.c_int
-    lib.md_newton_batch.argtypes = [i, P, i, P, i, P, P, P, P, i, P, P, P, i, i, i, i, i, i, P, P]
+    lib.md_newton_batch.argtypes = [i, P, i, P, i, P, P, P, P, i, P, P, P, i, i, i, i, i, i, i,
+                                    P, P]
     lib.md_batch_lds_bytes.argtypes = [i] * 4
     lib.md_batch_lds_bytes.restype = ctypes.c_size_t
     fake = P(4096)
 
-    def call(npaths=4, njobs=4, nq=1, iters=1, max_m=4, max_d=8, max_deg=3, grid=16, block=256,
-             ew=4, paths=fake):
+    def call(npaths=4, njobs=4, nq=1, iters=1, max_m=4, max_N=64, max_d=8, max_deg=3, grid=16,
+             block=256, ew=4, paths=fake):
         return lib.md_newton_batch(npaths, paths, njobs, fake, nq, fake, fake, fake, fake, iters,
-                                   fake, fake, fake, max_m, max_d, max_deg, grid, block, ew, None,
-                                   None)
+                                   fake, fake, fake, max_m, max_N, max_d, max_deg, grid, block, ew,
+                                   None, None)
     # penta double paths are not carried by the batched kernel: rejected on the host
     assert call(max_m=5) == 1
+    assert call(max_m=0) == 1
+    # neither are paths of more than 64 equations
+    assert call(max_N=65) == 2
+    assert b"max_N=65" in lib.md_last_error()
+    assert call(max_N=70, npaths=0) == 2      # refused before the empty-batch early return
+    assert call(max_N=0) == 2
     assert call(grid=0) == 1
     assert call(ew=5) == 1                      # more evaluation waves than the block has
     assert call(block=512, ew=9) == 1

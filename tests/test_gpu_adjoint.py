@@ -148,3 +148,45 @@ def test_autograd_newton_solve(B, store):
     assert dd_rel_err(g[:, :2], want) <= bound(m, sysm, d)
     want_L = float(np.sum(xs[:, 0] ** 2))
     assert abs(float(L.detach()) - want_L) <= 1e-13 * want_L
+
+
+def test_sum_abs2_backward_keeps_every_limb(B):
+    """SumAbs2's backward is 2 g z formed in the library (md x double per
+    plane): with an upstream g = 3 (not a power of two) it equals the
+    oracle's md x double product by 6 bit for bit, in all m limbs."""
+    from paper_2012_06607_amd.autograd import sum_abs2
+    m = 4
+    z = I.unit_complex(I.rng(1207, 0), m, 5, 7)
+    zt = dev(z).requires_grad_()
+    L = 3.0 * sum_abs2(zt)
+    L.backward()
+    got = host(zt.grad)
+    six = np.zeros((m, 35))
+    six[0] = 6.0
+    for part in range(2):
+        want = oracle.elementwise("muld", z[part].reshape(m, -1), six).reshape(m, 5, 7)
+        assert np.array_equal(got[part], want)
+    assert np.any(got[:, 1:] != 0)     # the lower limbs are there
+
+
+def test_autograd_upstream_three(B):
+    """coef.grad of 3 sum |x|^2 through newton_solve: the upstream 3 reaches
+    the adjoint as G = 6 x with every limb, so the gradient is the oracle's
+    adjoint for G = 6 x (formed by the oracle's md x double product)."""
+    from paper_2012_06607_amd.autograd import newton_solve, sum_abs2
+    m, d, n, iters = 4, 8, 8, 8
+    sysm, x0 = I.newton_system((1206, 0), n, m, terms=6)
+    xs, _, _ = oracle.newton(sysm, I.series_start(x0, d), iters)
+    G = np.empty_like(xs)
+    six = np.zeros((m, xs[0].size // m))
+    six[0] = 6.0
+    for part in range(2):
+        G[part] = oracle.elementwise("muld", xs[part].reshape(m, -1), six).reshape(xs[part].shape)
+    want, _ = oracle.newton_adjoint(sysm, xs, G)
+    sysd = B.DeviceSystem(sysm)
+    coef = dev(sysm.coef).requires_grad_()
+    x, st = newton_solve(coef, sysd, dev(I.series_start(x0, d)), iters)
+    (3.0 * sum_abs2(x)).backward()
+    g = host(coef.grad)
+    assert int(host(st)[0]) == 0
+    assert dd_rel_err(g[:, :2], want) <= bound(m, sysm, d)

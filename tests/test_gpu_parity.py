@@ -357,6 +357,30 @@ def test_newton_deterministic(B):
     assert np.array_equal(outs[0], outs[1])
 
 
+def test_newton_diverged_flag(B):
+    """MD_ST_DIVERGED: dx_norm carries the previous step's |dx_d| in; the bit
+    is set when the new |dx_d| is larger, and not when the input is zero
+    (no previous step) or larger than the new one."""
+    m, d = 2, 6
+    sysm, x0 = I.newton_system((6, 1), 5, m)
+    sd = B.DeviceSystem(sysm)
+    x = I.series_start(x0, d)
+    _, nrm, st = B.md_newton_step(sd, dev(x))
+    first = host(nrm).copy()
+    assert int(host(st)[0]) == 0 and first[0, 0] > 0
+    for prev, want in ((0.0, 0), (first[0, 0] * 0.5, B.MD_ST_DIVERGED),
+                       (first[0, 0] * 2.0, 0)):
+        nin = torch.zeros((m, 2), dtype=torch.float64, device="cuda")
+        nin[0, 0] = prev
+        _, nout, st = B.md_newton_step(sd, dev(x), dx_norm=nin)
+        assert (int(host(st)[0]) & B.MD_ST_DIVERGED) == want, (prev, first[0, 0])
+        assert np.array_equal(host(nout), first)   # the output norms do not depend on the input
+    # equal values are not growth
+    nin = torch.as_tensor(first, device="cuda").clone()
+    _, _, st = B.md_newton_step(sd, dev(x), dx_norm=nin)
+    assert int(host(st)[0]) == 0
+
+
 def test_newton_nonfinite_flag(B):
     m, d = 2, 4
     sysm, x0 = I.newton_system((6, 0), 4, m)

@@ -102,3 +102,28 @@ def test_cpu_baseline_pool():
     r = bench.cpu_baseline(paths, 0.3, 2)
     assert r["kind"] == "oracle" and r["cores"] == 2 and r["unit"] == "Newton steps/s"
     assert r["value"] > 0 and "2 worker processes" in r["sample"]
+
+
+def test_batch_refuses_paths_the_kernel_does_not_carry():
+    """BatchedPaths refuses, on the host, a path above 64 equations, with
+    N < n, or in a precision above quad double, so that md_newton_batch is
+    never given one (its kernel would only flag it MD_ST_BADPATH)."""
+    paths = tiny_paths(3)
+    m, n = 2, 70
+    one = ([1.0] + [0.0] * (m - 1), [0.0] * m)
+    mone = ([-1.0] + [0.0] * (m - 1), [0.0] * m)
+    big = I.build_system(n, n, m, 0, [[((i,), [one]), ((), [mone])] for i in range(n)])
+    with pytest.raises(B.MdError, match="N <= 64"):
+        B.BatchedPaths(paths + [(big, np.zeros((2, m, 3, n)))], device="cpu")
+    # fewer equations than unknowns
+    under = I.build_system(2, 3, m, 0, [[((0,), [one]), ((), [mone])],
+                                        [((1, 2), [one]), ((), [mone])]])
+    with pytest.raises(B.MdError, match="n <= N"):
+        B.BatchedPaths([(under, np.zeros((2, m, 3, 3)))], device="cpu")
+    # penta double
+    sys5, x5 = I.newton_system((995, 0), 3, 5, terms=3, max_deg=2)
+    with pytest.raises(B.MdError, match="m=5"):
+        B.BatchedPaths(paths + [(sys5, I.series_start(x5, 2))], device="cpu")
+    # the largest accepted shapes pass, and the batch records its maxima
+    batch = B.BatchedPaths(paths, device="cpu")
+    assert batch.max_N == max(s.N for s, _ in paths) and batch.max_m <= 4
