@@ -276,34 +276,45 @@ __global__ void __launch_bounds__(BLOCK) k_newton_batch(int npaths, const md_pat
   __shared__ int sh_job;
   const int q = nq == 1 ? 0 : xcc_id() % nq;
   const int begin = qbegin[q], end = qbegin[q + 1];
-  while (true) {
-    if (threadIdx.x == 0) sh_job = begin + atomicAdd(counters + q, 1);
-    __syncthreads();
-    const int job = sh_job;
-    __syncthreads();
-    if (job >= end) break;
+  // Every single-thread action of the job loop (taking the next job, the
+  // status of a refused path, the path's end clock) sits in one leader block
+  // between two barriers, and the loop has no other exit or back edge.  A
+  // leader-only block at the loop head with a `continue` elsewhere lets the
+  // compiler route the other lanes' back edge around it straight to the
+  // barrier; the loop then becomes divergent and those lanes spin on a stale
+  // job while the leader waits, masked off, for them to leave.
+  if (threadIdx.x == 0) sh_job = begin + atomicAdd(counters + q, 1);
+  __syncthreads();
+  int job = __builtin_amdgcn_readfirstlane(sh_job);
+  while (job < end) {
     const int path = jobs[2 * job];
     const int G = jobs[2 * job + 1] >> 8, member = jobs[2 * job + 1] & 0xff;
-    if (path < 0 || path >= npaths) continue;
-    const md_path p = paths[path];
-    const bool ok = G >= 1 && member < G && p.N >= p.n && p.n >= 1 && p.N <= WAVE &&
-                    p.d >= 0 && p.max_deg >= 0 && p.m >= 1 && p.m <= 4;
-    if (!ok) {
-      if (threadIdx.x == 0) atomicOr(status + path, MD_ST_BADPATH);
-      continue;
+    const bool known = path >= 0 && path < npaths;
+    bool ok = false;
+    md_path p{};
+    if (known) {
+      p = paths[path];
+      ok = G >= 1 && member < G && p.N >= p.n && p.n >= 1 && p.N <= WAVE && p.d >= 0 &&
+           p.max_deg >= 0 && p.m >= 1 && p.m <= 4;
     }
-    if (clk && threadIdx.x == 0 && member == 0) clk[2 * path] = wall_clock64();
-    int32_t *gc = gang_ctr + path;
-    switch (p.m) {
-      case 1: newton_path<1>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc); break;
-      case 2: newton_path<2>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc); break;
-      case 3: newton_path<3>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc); break;
-      case 4: newton_path<4>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc); break;
-      default:
-        if (threadIdx.x == 0) atomicOr(status + path, MD_ST_BADPATH);
-        break;
+    if (ok) {
+      if (clk && threadIdx.x == 0 && member == 0) clk[2 * path] = wall_clock64();
+      int32_t *gc = gang_ctr + path;
+      switch (p.m) {
+        case 1: newton_path<1>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc); break;
+        case 2: newton_path<2>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc); break;
+        case 3: newton_path<3>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc); break;
+        default: newton_path<4>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc); break;
+      }
     }
-    if (clk && threadIdx.x == 0 && member == 0) clk[2 * path + 1] = wall_clock64();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (known && !ok) atomicOr(status + path, MD_ST_BADPATH);
+      if (ok && clk && member == 0) clk[2 * path + 1] = wall_clock64();
+      sh_job = begin + atomicAdd(counters + q, 1);
+    }
+    __syncthreads();
+    job = __builtin_amdgcn_readfirstlane(sh_job);
   }
 }
 

@@ -14,7 +14,11 @@ namespace mds {
 
 // ---------------------------------------------------------------------------
 // 1/sqrt(a) by Newton steps y += y (1 - a y^2)/2 that double the working
-// precision (2, 4, 8 limbs, then M), from the hardware value.
+// precision (2, 4, 8 limbs, then M), from the hardware value.  A step
+// squares the relative error (times 3/2), and a double-double value is good
+// to about 2^-104 rather than 2^-106, so a step from it reaches only about
+// 2^-207: short of four limbs (2^-212), and a step from that short of eight
+// (2^-424).  For M = 4 and M = 8 one more step at full precision follows.
 
 template <int P, int M>
 __device__ __forceinline__ mdr<P> trunc(const mdr<M> &a) {
@@ -45,12 +49,16 @@ __device__ __forceinline__ mdr<M> rsqrt_doubling(const mdr<M> &a) {
     mdr<2> y2 = rsqrt_step<2, M>(a, md_from<2>(y0));
     if constexpr (M == 2) {
       return rsqrt_step<2, 2>(a, y2);
-    } else if constexpr (M <= 4) {
+    } else if constexpr (M == 3) {
       return rsqrt_step<M, M>(a, trunc<M, 2>(y2));
+    } else if constexpr (M == 4) {
+      return rsqrt_step<M, M>(a, rsqrt_step<M, M>(a, trunc<M, 2>(y2)));
     } else {
       mdr<4> y4 = rsqrt_step<4, M>(a, trunc<4, 2>(y2));
-      if constexpr (M <= 8) {
+      if constexpr (M < 8) {
         return rsqrt_step<M, M>(a, trunc<M, 4>(y4));
+      } else if constexpr (M == 8) {
+        return rsqrt_step<M, M>(a, rsqrt_step<M, M>(a, trunc<M, 4>(y4)));
       } else {
         mdr<8> y8 = rsqrt_step<8, M>(a, trunc<8, 4>(y4));
         return rsqrt_step<M, M>(a, trunc<M, 8>(y8));

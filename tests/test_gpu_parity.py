@@ -311,10 +311,13 @@ def newton_compare(B, sysm, x, iters, m):
             assert e[k] <= tol(m, math.log2(cond) + math.log2(k + 1) + 4), (it, k, e)
         assert int(host(st)[0]) == stw == 0
         nh = host(nrm)
-        # near convergence the update is rounding noise: compare at the level
-        # of the precision relative to the last coefficient
-        xd = max(1.0, np.abs(xw[0, 0, -1] + 1j * xw[1, 0, -1]).max())
-        assert abs(nh[0, 0] - nrmw[0, 0]) <= 1e-6 * nrmw[0, 0] + 2.0 ** -(53 * m - 16) * xd
+        # |dx_d| is the difference of x_d between two steps, so the two sides
+        # may differ by what their x_d may differ by (the bound above at
+        # k = d), relative to the larger of |x_d|, the update and 1
+        d = xw.shape[2] - 1
+        scale = max(1.0, np.abs(xw[0, 0, -1] + 1j * xw[1, 0, -1]).max(), nrmw[0, 0])
+        dn = abs(nh[0, 0] - nrmw[0, 0])
+        assert dn <= tol(m, math.log2(cond) + math.log2(d + 1) + 4) * scale, (it, dn, scale)
         x = xw  # continue both from the oracle's iterate
         xg = dev(x)
     return x, nh
@@ -364,7 +367,11 @@ def test_newton_diverged_flag(B):
     m, d = 2, 6
     sysm, x0 = I.newton_system((6, 1), 5, m)
     sd = B.DeviceSystem(sysm)
-    x = I.series_start(x0, d)
+    # the first step from a constant series leaves coefficients 2..d alone
+    # (A(t) = A_0), so the flag is exercised from the second step's input
+    xg = dev(I.series_start(x0, d))
+    B.md_newton_step(sd, xg)
+    x = host(xg).copy()
     _, nrm, st = B.md_newton_step(sd, dev(x))
     first = host(nrm).copy()
     assert int(host(st)[0]) == 0 and first[0, 0] > 0
@@ -505,17 +512,27 @@ def test_batch_graph_replays(B):
             assert np.array_equal(host(batch.x(p)), eager[p]), (rep, p)
 
 
-@pytest.mark.skip(reason="stalled twice on the GPU without a cause found in the code yet; "
-                         "kept off the GPU until one is shown")
-def test_batch_flags_paths_above_64_unknowns(B):
-    paths = small_batch(count=3, seed=2)
-    # N above 64: x_i - 1 = 0 for 70 unknowns, built directly
-    m, n = 2, 70
-    one = ([1.0] + [0.0] * (m - 1), [0.0] * m)
-    mone = ([-1.0] + [0.0] * (m - 1), [0.0] * m)
-    sysm = I.build_system(n, n, m, 0, [[((i,), [one]), ((), [mone])] for i in range(n)])
-    x0 = np.zeros((2, m, 3, n))
-    batch = B.BatchedPaths(paths + [(sysm, x0)])
-    B.md_newton_batch(batch, 1)
+def test_batch_flags_refused_paths(B):
+    """A path table that breaks the kernel's limits anyway (the host refuses
+    such paths, so the table is altered on the device after construction):
+    a path that claims 70 equations and one that claims penta double get
+    MD_ST_BADPATH and are not run; the others run as in a batch without
+    them, and the launch ends (every workgroup leaves the job loop)."""
+    paths = small_batch(count=5, seed=2)
+    ref = B.BatchedPaths(paths)
+    B.md_newton_batch(ref, 2, block=512)
+    batch = B.BatchedPaths(paths)
+    t = batch.table.copy()
+    t[3]["N"] = 70
+    t[1]["m"] = 5
+    batch.paths_dev.copy_(torch.as_tensor(t.view(np.uint8).copy(), device="cuda"))
+    print("refused-path launch: paths 1 (m=5) and 3 (N=70) of 5", flush=True)
+    B.md_newton_batch(batch, 2, block=512)
     st = host(batch.status)
-    assert st[3] & 4 and not st[:3].any()
+    assert st[1] == B.MD_ST_BADPATH | B.MD_ST_NOTRUN and st[3] == B.MD_ST_BADPATH | B.MD_ST_NOTRUN, st
+    assert not st[[0, 2, 4]].any(), st
+    assert not host(ref.status).any()
+    for p in (0, 2, 4):
+        assert np.array_equal(host(batch.x(p)), host(ref.x(p))), p
+    for p in (1, 3):
+        assert np.array_equal(host(batch.x(p)), paths[p][1]), p     # untouched

@@ -162,9 +162,10 @@ def config4_sample():
     branch below)."""
     specs = I.batch_specs((4, 0), 1024)
     big_qd = [s for s in specs if s.m == 4 and s.n == 64 and s.d == 32]
-    dd64 = [s for s in specs if s.m == 2 and s.n == 64 and s.d >= 31]
+    dd64 = ([s for s in specs if s.m == 2 and s.n == 64 and s.d == 32][:1]
+            + [s for s in specs if s.m == 2 and s.n == 64 and s.d == 31][:1])
     qd_small = [s for s in specs if s.m == 4 and s.n <= 24 and s.d >= 31]
-    pick = big_qd[:1] + dd64[:2] + qd_small[:1]
+    pick = big_qd[:1] + dd64 + qd_small[:1]
     out = []
     for s in pick:
         sysm, x0 = I.newton_system((4, s.path), s.n, s.m)
