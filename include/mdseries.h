@@ -157,6 +157,24 @@ int md_series_solve(int m, int N, int n, int d, const double *QR, const double *
 int md_newton_step(int m, int d, const md_system *sys, double *x, double *dx_norm, void *ws,
                    size_t ws_bytes, int32_t *status, void *stream);
 
+/* md_newton_step without a workspace argument, for callers that cannot
+ * allocate device memory (code under graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the step's scratch is a fixed device
+ * array of MD_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, taken
+ * at the first call on each device (the calling thread's current device,
+ * which must be the device of `stream`) and held until the process ends.
+ * The call allocates and frees nothing.  Arguments, layouts, results and
+ * bits are those of md_newton_step.  Every call on one GPU uses that GPU's
+ * one array, which keeps the last call's contents (nothing in it needs to
+ * start at zero): calls that may overlap on one GPU (other streams, other
+ * threads) race and must be serialised by the caller.
+ * Errors: as md_newton_step; MD_EWORKSPACE when the step needs more than
+ * MD_NOALLOC_SCRATCH_BYTES (md_workspace_bytes(MD_FN_NEWTON, ...) tells);
+ * MD_EHIP when the array's device address cannot be had. */
+#define MD_NOALLOC_SCRATCH_BYTES (32u << 20)
+int md_newton_step_noalloc(int m, int d, const md_system *sys, double *x, double *dx_norm,
+                           int32_t *status, void *stream);
+
 /* Gradient of a real loss L with respect to the series coefficients of the
  * system, through a converged series solution x(t) (the implicit function
  * of the system of Section 4 at its root).  With T(A) the block lower

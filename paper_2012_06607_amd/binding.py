@@ -55,6 +55,7 @@ def lib() -> ctypes.CDLL:
         L.md_qr.argtypes = [i32, i32, i32, P, P, P, P, P, P]
         L.md_series_solve.argtypes = [i32, i32, i32, i32, P, P, P, P, P, P, P, sz, P, P]
         L.md_newton_step.argtypes = [i32, i32, ctypes.POINTER(md_system), P, P, P, sz, P, P]
+        L.md_newton_step_noalloc.argtypes = [i32, i32, ctypes.POINTER(md_system), P, P, P, P]
         L.md_newton_adjoint.argtypes = [i32, i32, ctypes.POINTER(md_system), P, P, i32, P, P, sz,
                                         P, P]
         L.md_workspace_bytes.argtypes = [i32, i32, i32, i32, i32, i32, i32]
@@ -256,6 +257,26 @@ def md_newton_step(sysd: DeviceSystem, x: torch.Tensor, dx_norm=None, ws=None, s
     _check(lib().md_newton_step(m, L - 1, ctypes.byref(sysd.desc), _ptr(x), _ptr(dx_norm),
                                 _ptr(ws, torch.uint8), ws.numel(), _ptr(status, torch.int32),
                                 _stream(stream)), "md_newton_step")
+    return x, dx_norm, status
+
+
+MD_NOALLOC_SCRATCH_BYTES = 32 << 20
+
+
+def md_newton_step_noalloc(sysd: DeviceSystem, x: torch.Tensor, dx_norm: torch.Tensor,
+                           status: torch.Tensor, stream=None):
+    """md_newton_step with the library's fixed per-GPU scratch instead of a
+    workspace: the caller passes every buffer (x, dx_norm (m, 2), status
+    int32[1]) and nothing is allocated here or in the library."""
+    m = _limbs(x)
+    _, _, L, n = x.shape
+    if tuple(dx_norm.shape) != (m, 2) or dx_norm.dtype != torch.float64:
+        raise MdError("md_newton_step_noalloc: dx_norm must be float64 (m, 2)")
+    if status.dtype != torch.int32 or status.numel() < 1:
+        raise MdError("md_newton_step_noalloc: status must be int32 with one element")
+    _check(lib().md_newton_step_noalloc(m, L - 1, ctypes.byref(sysd.desc), _ptr(x),
+                                        _ptr(dx_norm), _ptr(status, torch.int32),
+                                        _stream(stream)), "md_newton_step_noalloc")
     return x, dx_norm, status
 
 

@@ -44,11 +44,12 @@ def check_device_asm(asm_path: str) -> list[str]:
     CALLABLE list, or that jump through s[30:31].  Returns their symbols."""
     text = open(asm_path).read()
     kernels = set(re.findall(r"\.name:\s+(\S+)", text))
+    functions = set(re.findall(r"\.type\s+(\S+),@function", text))
     labels = [(mm.start(), mm.group(1)) for mm in re.finditer(r"^(_Z\w+):", text, re.M)]
     bad = []
     for i, (pos, name) in enumerate(labels):
-        if name in kernels:
-            continue
+        if name in kernels or name not in functions:
+            continue  # kernels, and data (device variables) rather than code
         end = labels[i + 1][0] if i + 1 < len(labels) else len(text)
         if "s_getpc_b64 s[30:31]" in text[pos:end] or not any(c.match(name) for c in CALLABLE):
             bad.append(name)

@@ -2,6 +2,8 @@
 // differentiation, b = -f, one QR of A_0, the staggered solve, x += dx, and
 // the size of the update (Section 6: the modulus of the update to the last
 // coefficient).
+#include <mutex>
+
 #include "internal.hpp"
 #include "layout.hpp"
 
@@ -54,19 +56,15 @@ __global__ void __launch_bounds__(256) k_norms(int d, int n, const double *__res
 
 using namespace mds;
 
-extern "C" int md_newton_step(int m, int d, const md_system *sys, double *x, double *dx_norm,
-                              void *ws, size_t ws_bytes, int32_t *status, void *stream) {
-  if (!sys) return fail(MD_ENULL, "md_newton_step: null system");
-  if (d < 0) return fail(MD_EINVAL, "md_newton_step: d=%d < 0", d);
-  if (!valid_m(m)) return dispatch_m(m, [](auto) { return MD_OK; });
+namespace {
+
+int newton_step_impl(int m, int d, const md_system *sys, double *x, double *dx_norm, void *ws,
+                     size_t ws_bytes, int32_t *status, hipStream_t s, const char *who) {
   const int N = sys->N, n = sys->n;
-  if (n < 1 || N < n) return fail(MD_ESHAPE, "md_newton_step: need N >= n >= 1 (N=%d n=%d)", N, n);
-  if (!x) return fail(MD_ENULL, "md_newton_step: null x");
   NewtonLayout lay(m, N, n, d, sys->M, sys->max_deg);
   if (!ws || ws_bytes < lay.bytes || !aligned256(ws))
-    return fail(MD_EWORKSPACE, "md_newton_step: workspace %zu bytes < %zu or misaligned", ws_bytes,
+    return fail(MD_EWORKSPACE, "%s: workspace %zu bytes < %zu or misaligned", who, ws_bytes,
                 lay.bytes);
-  hipStream_t s = (hipStream_t)stream;
   char *w = static_cast<char *>(ws);
   double *f = reinterpret_cast<double *>(w + lay.off_f);
   double *A = reinterpret_cast<double *>(w + lay.off_A);
@@ -88,6 +86,73 @@ extern "C" int md_newton_step(int m, int d, const md_system *sys, double *x, dou
     if (blocks > 65536) blocks = 65536;
     k_update<Mm><<<dim3(unsigned(blocks)), dim3(256), 0, s>>>(E, dx, x);
     if (dx_norm) k_norms<Mm><<<dim3(1), dim3(256), 0, s>>>(d, n, dx, dx_norm, status);
-    return check_launch("md_newton_step (update)");
+    return check_launch(who);
   });
+}
+
+int newton_check(int m, int d, const md_system *sys, const double *x, const char *who) {
+  if (!sys) return fail(MD_ENULL, "%s: null system", who);
+  if (d < 0) return fail(MD_EINVAL, "%s: d=%d < 0", who, d);
+  if (!valid_m(m)) return dispatch_m(m, [](auto) { return MD_OK; });
+  if (sys->n < 1 || sys->N < sys->n)
+    return fail(MD_ESHAPE, "%s: need N >= n >= 1 (N=%d n=%d)", who, sys->N, sys->n);
+  if (!x) return fail(MD_ENULL, "%s: null x", who);
+  return MD_OK;
+}
+
+// The fixed scratch of md_newton_step_noalloc: one copy per GPU, held from
+// the library's load until the process ends.  Host code never passes this
+// name to a kernel (on the host it is a stand-in, not a device address): it
+// takes the device address from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) char scratch[MD_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_address(void **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(MD_EHIP, "md_newton_step_noalloc: hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(MD_EINVAL, "md_newton_step_noalloc: device %d outside 0..%d", dev, kMaxDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(MD_EHIP, "md_newton_step_noalloc: hipGetSymbolAddress of the scratch on device %d: %s",
+                  dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return MD_OK;
+}
+
+}  // namespace
+
+extern "C" int md_newton_step(int m, int d, const md_system *sys, double *x, double *dx_norm,
+                              void *ws, size_t ws_bytes, int32_t *status, void *stream) {
+  const int rc = newton_check(m, d, sys, x, "md_newton_step");
+  if (rc) return rc;
+  return newton_step_impl(m, d, sys, x, dx_norm, ws, ws_bytes, status, (hipStream_t)stream,
+                          "md_newton_step");
+}
+
+extern "C" int md_newton_step_noalloc(int m, int d, const md_system *sys, double *x,
+                                      double *dx_norm, int32_t *status, void *stream) {
+  const char *who = "md_newton_step_noalloc";
+  int rc = newton_check(m, d, sys, x, who);
+  if (rc) return rc;
+  const size_t need = NewtonLayout(m, sys->N, sys->n, d, sys->M, sys->max_deg).bytes;
+  if (need > MD_NOALLOC_SCRATCH_BYTES)
+    return fail(MD_EWORKSPACE,
+                "%s: this step needs %zu bytes of scratch, above the fixed %zu (use md_newton_step "
+                "with a workspace)",
+                who, need, size_t(MD_NOALLOC_SCRATCH_BYTES));
+  void *ws = nullptr;
+  rc = scratch_address(&ws);
+  if (rc) return rc;
+  return newton_step_impl(m, d, sys, x, dx_norm, ws, MD_NOALLOC_SCRATCH_BYTES, status,
+                          (hipStream_t)stream, who);
 }

@@ -147,3 +147,28 @@ def test_batch_host_checks(lib):
     lib.md_device_dies.argtypes = [P, i, P]
     assert lib.md_device_dies(None, 4, None) == 3
     assert lib.md_device_dies(fake, 0, None) == 1
+
+
+def test_noalloc_host_checks(lib):
+    """md_newton_step_noalloc refuses, before any device call, a step whose
+    scratch would not fit the fixed per-GPU array, and bad arguments."""
+    P = ctypes.c_void_p
+    lib.md_newton_step_noalloc.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(_System),
+                                           P, P, P, P]
+    lib.md_workspace_bytes.restype = ctypes.c_size_t
+    lib.md_workspace_bytes.argtypes = [ctypes.c_int] * 7
+    lib.md_last_error.restype = ctypes.c_char_p
+    fake = P(4096)
+    limit = 32 << 20
+    big = _System(64, 64, 1024, 1, 4, 4096, 4096, 4096, 4096)
+    assert lib.md_workspace_bytes(3, 10, 64, 64, 32, 1024, 4) > limit
+    assert lib.md_newton_step_noalloc(10, 32, ctypes.byref(big), fake, None, None, None) == 4
+    assert b"above the fixed 33554432" in lib.md_last_error()
+    small = _System(8, 8, 80, 1, 3, 4096, 4096, 4096, 4096)
+    assert lib.md_workspace_bytes(3, 2, 8, 8, 8, 80, 3) <= limit
+    assert lib.md_newton_step_noalloc(2, -1, ctypes.byref(small), fake, None, None, None) == 1
+    assert lib.md_newton_step_noalloc(6, 8, ctypes.byref(small), fake, None, None, None) == 1
+    assert lib.md_newton_step_noalloc(2, 8, None, fake, None, None, None) == 3
+    assert lib.md_newton_step_noalloc(2, 8, ctypes.byref(small), None, None, None, None) == 3
+    bad = _System(4, 8, 80, 1, 3, 4096, 4096, 4096, 4096)
+    assert lib.md_newton_step_noalloc(2, 8, ctypes.byref(bad), fake, None, None, None) == 2
