@@ -293,6 +293,43 @@ def newton_system(key, n: int, m: int, terms: int = 8, max_deg: int = 3,
     raise RuntimeError("no well conditioned system found")
 
 
+def augmented_system(key, sysm: System, extra: int = 7) -> System:
+    """N = n + extra equations in n unknowns that are consistent exactly:
+    the first n equations are those of the square system `sysm`, and each
+    appended one is 2^a f_i + 2^b f_j for a random pair i != j and
+    a, b in {-1, 0, 1}, written as the two equations' terms side by side
+    with their coefficients scaled (powers of two scale exactly, and the
+    terms are not merged).  Every solution series of the square system
+    solves the augmented one with zero residual, so the least-squares
+    Newton step (QR of the N x n matrix A_0) has the square system's
+    solution as its fixed point (Section 4, N >= n; Section 6 augments a
+    square system with extra equations in the same way in spirit)."""
+    g = rng(*key)
+    equations = []
+    for i in range(sysm.N):
+        eq = []
+        for j, fac in sysm.terms(i):
+            eq.append((fac, [(sysm.coef[0, :, j, k], sysm.coef[1, :, j, k])
+                             for k in range(sysm.dc + 1)]))
+        equations.append(eq)
+    pairs = []
+    for _ in range(extra):
+        i, j = (int(v) for v in g.choice(sysm.N, size=2, replace=False))
+        a, b = (int(v) for v in g.integers(-1, 2, size=2))
+        pairs.append((i, j, a, b))
+        eq = []
+        for src, e in ((i, a), (j, b)):
+            sc = math.ldexp(1.0, e)
+            for t, fac in sysm.terms(src):
+                eq.append((fac, [(sysm.coef[0, :, t, k] * sc, sysm.coef[1, :, t, k] * sc)
+                                 for k in range(sysm.dc + 1)]))
+        equations.append(eq)
+    out = build_system(sysm.N + extra, sysm.n, sysm.m, sysm.dc, equations)
+    out.meta = dict(sysm.meta)
+    out.meta["appended"] = pairs
+    return out
+
+
 def series_start(x0: np.ndarray, d: int) -> np.ndarray:
     """x(t) = x0 + 0 t + ... as planes (2, m, d+1, n)."""
     two, m, n = x0.shape

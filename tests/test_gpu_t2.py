@@ -219,3 +219,63 @@ def test_config4_sample_batched_against_oracle(B):
         eg = planes_rel_err_per_k(pad_limbs(got[p], 8, 1), xr)
         eo = planes_rel_err_per_k(pad_limbs(xw, 8, 1), xr)
         check_t2(eg, eo, m, f"cfg4 path {s.path} n={s.n} d={s.d} m={m} (4 steps, batched)")
+
+
+# ----------------------------------------------------------------------------
+# least squares: N = n + 7 equations (Section 4, N >= n; Section 6 augments a
+# square system with 7 equations)
+
+
+@pytest.mark.parametrize("m,n,d,steps", ((4, 32, 16, (0, 3, 7)), (2, 64, 8, (4,))))
+def test_t2_overdetermined_newton(B, m, n, d, steps):
+    """md_newton_step on a consistent system of n + 7 equations in n
+    unknowns (the least-squares QR of an (n+7) x n A_0), against the exact
+    least-squares step at 2000 bits, next to the oracle."""
+    sysm, x0 = I.newton_system((1300, m, n), n, m)
+    aug = I.augmented_system((1301, m, n), sysm, 7)
+    assert aug.N == n + 7
+    newton_t2(B, aug, I.series_start(x0, d), set(steps), f"N={n + 7} n={n} m={m} d={d}")
+
+
+def test_batched_overdetermined_paths_against_oracle(B):
+    """Paths of n + 7 equations in n unknowns (N up to 47) next to a square
+    path in one batched launch, 4 Newton steps, against each path's 4 steps
+    by the oracle in octo double (T2 rule), a gang of 2 on the largest."""
+    cases = ((12, 10, 2), (24, 16, 4), (40, 12, 2), (17, 20, 4), (20, 9, 2))
+    paths = []
+    for idx, (n, d, m) in enumerate(cases):
+        sysm, x0 = I.newton_system((1310, idx), n, m)
+        if idx < 4:
+            sysm = I.augmented_system((1311, idx), sysm, 7)
+        paths.append((sysm, I.series_start(x0, d)))
+    iters = 4
+    print("overdetermined batch:", [(s.N, s.n, s.m, x.shape[2] - 1) for s, x in paths], flush=True)
+
+    def ref_run(i):
+        sysm, x = paths[i]
+        return oracle.newton(padded_system(sysm, 8), pad_limbs(x, 8, 1), iters)
+
+    def orc_run(i):
+        sysm, x = paths[i]
+        return oracle.newton(sysm, x, iters)
+
+    with cf.ThreadPoolExecutor(max_workers=2 * len(paths)) as ex:
+        refs = [ex.submit(ref_run, i) for i in range(len(paths))]
+        orcs = [ex.submit(orc_run, i) for i in range(len(paths))]
+        batch = B.BatchedPaths(paths)
+        gangs = np.ones(len(paths), dtype=np.int64)
+        gangs[int(np.argmax(batch.cost))] = 2
+        batch.set_schedule(gangs=gangs)
+        B.md_newton_batch(batch, iters, block=512)
+        st = host(batch.status)
+        got = [host(batch.x(p)).copy() for p in range(len(paths))]
+        refs = [f.result() for f in refs]
+        orcs = [f.result() for f in orcs]
+    assert not st.any(), st
+    for p, (sysm, _) in enumerate(paths):
+        xr, _, str_ = refs[p]
+        xw, _, stw = orcs[p]
+        assert str_ == 0 and stw == 0
+        eg = planes_rel_err_per_k(pad_limbs(got[p], 8, 1), xr)
+        eo = planes_rel_err_per_k(pad_limbs(xw, 8, 1), xr)
+        check_t2(eg, eo, sysm.m, f"batched N={sysm.N} n={sysm.n} m={sysm.m}")

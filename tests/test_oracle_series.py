@@ -331,3 +331,39 @@ def test_newton_steps_against_2000_bit_reference(m):
         x = xo
     # converged: the update to the last coefficient is at the noise level
     assert nrm[0, 0] <= 2.0 ** -(53 * m - 12)
+
+
+@pytest.mark.parametrize("m", (2, 4))
+def test_least_squares_newton_on_a_consistent_overdetermined_system(m):
+    """N = n + 7 (Section 4: N >= n, least squares by the QR of A_0; the
+    experiment of Section 6 augments a square system with 7 equations): the
+    appended equations are exact combinations of the first n, so the exact
+    least-squares step equals the exact step of the square system, and the
+    oracle's least-squares Newton converges to the square system's series."""
+    n, d = 6, 8
+    sysm, x0 = I.newton_system((920, m), n, m)
+    aug = I.augmented_system((921, m), sysm, 7)
+    assert (aug.N, aug.n) == (n + 7, n)
+    x = I.series_start(x0, d)
+    for it in range(6):
+        xo, nrm, st = oracle.newton_step(aug, x)
+        assert st == 0
+        ref_sq, _ = mp_newton_step(sysm, mp_array(x))
+        ref_ls, _ = mp_newton_step(aug, mp_array(x))
+        # consistency: the two exact steps agree far below the precision
+        for k in range(d + 1):
+            for i in range(n):
+                assert abs(ref_sq[k, i] - ref_ls[k, i]) <= mpmath.mpf(2) ** -1500 * (1 + abs(ref_sq[k, i]))
+        e = rel_err_per_k(xo, ref_sq)
+        cond = sysm.meta["cond_A0_double"]
+        for k in range(d + 1):
+            assert e[k] <= tol(m, math.log2(cond) + math.log2(k + 1) + 2), (it, k, e)
+        x = xo
+    # converged: the update to the last coefficient is at the precision's
+    # level relative to that coefficient
+    xd = np.abs(x[0, 0, d] + 1j * x[1, 0, d]).max()
+    assert nrm[0, 0] <= 2.0 ** -(53 * m - 12) * max(1.0, xd)
+    # the same series as Newton on the square system
+    xs, _, _ = oracle.newton(sysm, I.series_start(x0, d), 6)
+    e = rel_err_per_k(x, mp_array(xs))
+    assert np.all(e <= tol(m, 12)), e
