@@ -157,6 +157,41 @@ int md_series_solve(int m, int N, int n, int d, const double *QR, const double *
 int md_newton_step(int m, int d, const md_system *sys, double *x, double *dx_norm, void *ws,
                    size_t ws_bytes, int32_t *status, void *stream);
 
+/* Newton's method over increasing truncation degrees, as in the experiment
+ * of Section 6: for each degree d_j of `degrees` (increasing, at most
+ * MD_PROTOCOL_MAX_DEGREES of them) the iterate starts from the given point
+ * (x(t) = x0, higher coefficients zero) and takes Newton steps until the
+ * modulus of the update to its last coefficient, |dx_{d_j}| = max_i
+ * |dx_{d_j,i}|, is at most `tol` (the paper: 1e-32) or maxit[j] steps are
+ * done (the paper: 8, 8, 12, 16 for degrees 8, 16, 24, 32).  The test is
+ * applied from step min_steps on (2 in the tests: the first step from a
+ * constant series reaches only the coefficients its right-hand side has,
+ * x_1 when t enters the equations linearly, so its update to x_{d_j} is
+ * zero without saying anything about convergence).  A degree that
+ * ends with |dx_{d_j}| above `diverge` stops the protocol: the later degrees
+ * are not run (the paper's rule that a degree with too large an update ends
+ * the computations; the bound is a reading, 1.0 in the tests) and
+ * MD_ST_DIVERGED is set.  The decisions are taken on the device: the steps
+ * of every degree are enqueued ahead, and each of their kernels returns at
+ * once when its degree has converged or was not run, so the call never
+ * synchronises and can be captured in a graph.
+ * x0: planes (2, m, n) (n = sys->n); degrees, maxit: HOST int32[ndeg];
+ * x: planes (2, m, dmax+1, n), dmax = degrees[ndeg-1]: the series of the last
+ * degree that ran (zero above that degree); iters: device int32[ndeg], the
+ * steps taken at each degree (0 for a degree not run); norms: device real
+ * planes (m, ndeg), the last |dx_{d_j}| of each degree (0 if not run).
+ * Each degree's steps are md_newton_step's, so its series equals iters[j]
+ * calls of md_newton_step from series_start(x0, d_j) bit for bit.
+ * Workspace: md_workspace_bytes(MD_FN_PROTOCOL, m, N, n, dmax, M, max_deg).
+ * Errors: as md_newton_step; MD_EINVAL for an empty, too long or not
+ * increasing degree list, a negative step limit, min_steps < 1, tol < 0 or
+ * diverge <= 0. */
+#define MD_PROTOCOL_MAX_DEGREES 16
+int md_newton_protocol(int m, const md_system *sys, const double *x0, int ndeg,
+                       const int32_t *degrees, const int32_t *maxit, int min_steps, double tol,
+                       double diverge, double *x, int32_t *iters, double *norms, void *ws,
+                       size_t ws_bytes, int32_t *status, void *stream);
+
 /* md_newton_step without a workspace argument, for callers that cannot
  * allocate device memory (code under graph capture, tight serving loops,
  * harnesses that forbid hipMalloc): the step's scratch is a fixed device
@@ -201,7 +236,14 @@ int md_newton_adjoint(int m, int d, const md_system *sys, const double *x, const
                       int32_t *status, void *stream);
 
 /* Workspace size in bytes for an entry point (fn one of MD_FN_*). */
-enum { MD_FN_EVAL = 1, MD_FN_SOLVE = 2, MD_FN_NEWTON = 3, MD_FN_ADJOINT = 4, MD_FN_ADJOINT_STORE = 5 };
+enum {
+  MD_FN_EVAL = 1,
+  MD_FN_SOLVE = 2,
+  MD_FN_NEWTON = 3,
+  MD_FN_ADJOINT = 4,
+  MD_FN_ADJOINT_STORE = 5,
+  MD_FN_PROTOCOL = 6 /* md_newton_protocol; d is the largest degree */
+};
 size_t md_workspace_bytes(int fn, int m, int N, int n, int d, int M, int max_deg);
 
 /* One multiple-double operation per element, the units of Table 1, for

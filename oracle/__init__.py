@@ -14,6 +14,7 @@ import ctypes
 import os
 import subprocess
 import threading
+from fractions import Fraction
 
 import numpy as np
 
@@ -34,6 +35,7 @@ COUNTERS = ("add", "sub", "mul", "div", "fma", "sqrt", "md_add", "md_mul", "md_d
 
 ST_SINGULAR = 1
 ST_NONFINITE = 2
+ST_DIVERGED = 32
 
 CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
 
@@ -198,6 +200,55 @@ def newton(sysm, x: np.ndarray, iters: int):
         norms.append(nrm)
         status |= st
     return x, norms, status
+
+
+def _value(limbs) -> Fraction:
+    """Exact value of a limb expansion."""
+    return sum((Fraction(float(v)) for v in limbs), Fraction(0))
+
+
+def newton_protocol(sysm, x0: np.ndarray, degrees, maxit, tol: float, diverge: float,
+                    min_steps: int = 2):
+    """Newton's method over increasing truncation degrees (Section 6): for
+    each degree d_j, start from x(t) = x0 (higher coefficients zero) and
+    take Newton steps until the modulus of the update to the last
+    coefficient is at most tol (tested from step min_steps on: the first
+    step from a constant series reaches only x_1 when t enters linearly), or
+    maxit[j] steps are done; a degree that
+    ends with that modulus above `diverge` ends the computations (the later
+    degrees are not done).  The decisions compare exact values of the
+    multiple-double norms with the double thresholds.
+
+    x0: planes (2, m, n).  Returns (x planes (2, m, dmax+1, n): the series of
+    the last degree done, zero above it; iters: steps per degree (0 when not
+    done); norms: real planes (m, ndeg), the last modulus per degree (0 when
+    not done); status: OR of the steps' status words, and ST_DIVERGED when a
+    degree ended above the bound)."""
+    x0 = _c(x0)
+    _, m, n = x0.shape
+    dmax = int(degrees[-1])
+    x_out = np.zeros((2, m, dmax + 1, n))
+    iters = [0] * len(degrees)
+    norms = np.zeros((m, len(degrees)))
+    status = 0
+    tol_q, div_q = Fraction(tol), Fraction(diverge)
+    for j, (d, mi) in enumerate(zip(degrees, maxit)):
+        x = np.zeros((2, m, int(d) + 1, n))
+        x[:, :, 0, :] = x0
+        nrm = np.zeros((m, 2))
+        for _ in range(int(mi)):
+            x, nrm, st = newton_step(sysm, x)
+            status |= st
+            iters[j] += 1
+            if iters[j] >= min_steps and _value(nrm[:, 0]) <= tol_q:
+                break
+        norms[:, j] = nrm[:, 0]
+        x_out[:] = 0.0
+        x_out[:, :, :int(d) + 1, :] = x
+        if _value(nrm[:, 0]) > div_q:
+            status |= ST_DIVERGED
+            break
+    return x_out, iters, norms, status
 
 
 def newton_adjoint(sysm, x: np.ndarray, grad_x: np.ndarray):

@@ -20,6 +20,8 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libmdseries.so")
 
 MD_FN_EVAL, MD_FN_SOLVE, MD_FN_NEWTON, MD_FN_ADJOINT, MD_FN_ADJOINT_STORE = 1, 2, 3, 4, 5
+MD_FN_PROTOCOL = 6
+MD_PROTOCOL_MAX_DEGREES = 16
 MD_ST_SINGULAR, MD_ST_NONFINITE, MD_ST_BADPATH, MD_ST_GANG, MD_ST_NOTRUN = 1, 2, 4, 8, 16
 MD_ST_DIVERGED = 32
 OPS = {"add": 0, "sub": 1, "mul": 2, "div": 3, "sqrt": 4, "rsqrt": 5, "muld": 6,
@@ -56,6 +58,8 @@ def lib() -> ctypes.CDLL:
         L.md_series_solve.argtypes = [i32, i32, i32, i32, P, P, P, P, P, P, P, sz, P, P]
         L.md_newton_step.argtypes = [i32, i32, ctypes.POINTER(md_system), P, P, P, sz, P, P]
         L.md_newton_step_noalloc.argtypes = [i32, i32, ctypes.POINTER(md_system), P, P, P, P]
+        L.md_newton_protocol.argtypes = [i32, ctypes.POINTER(md_system), P, i32, P, P, i32,
+                                         ctypes.c_double, ctypes.c_double, P, P, P, P, sz, P, P]
         L.md_newton_adjoint.argtypes = [i32, i32, ctypes.POINTER(md_system), P, P, i32, P, P, sz,
                                         P, P]
         L.md_workspace_bytes.argtypes = [i32, i32, i32, i32, i32, i32, i32]
@@ -258,6 +262,42 @@ def md_newton_step(sysd: DeviceSystem, x: torch.Tensor, dx_norm=None, ws=None, s
                                 _ptr(ws, torch.uint8), ws.numel(), _ptr(status, torch.int32),
                                 _stream(stream)), "md_newton_step")
     return x, dx_norm, status
+
+
+def md_newton_protocol(sysd: DeviceSystem, x0: torch.Tensor, degrees=(8, 16, 24, 32),
+                       maxit=(8, 8, 12, 16), tol: float = 1e-32, diverge: float = 1.0,
+                       min_steps: int = 2, ws=None, status=None, stream=None):
+    """Newton's method over increasing truncation degrees from the point x0
+    (planes (2, m, n)), each degree from x0, until |dx_d| <= tol (tested
+    from step min_steps on) or maxit steps; a degree ending above `diverge`
+    stops the later ones.  Returns
+    (x planes (2, m, dmax+1, n), iters int32 (ndeg,), norms (m, ndeg),
+    status); all decisions are taken on the device."""
+    m = _limbs(x0)
+    if x0.dim() != 3 or x0.shape[2] != sysd.n:
+        raise MdError("md_newton_protocol: x0 must have shape (2, m, n)")
+    deg = np.ascontiguousarray(degrees, dtype=np.int32)
+    mit = np.ascontiguousarray(maxit, dtype=np.int32)
+    if deg.ndim != 1 or deg.shape != mit.shape or deg.size < 1:
+        raise MdError("md_newton_protocol: degrees and maxit must be equal-length lists")
+    dmax = int(deg[-1])
+    h = sysd.host
+    if ws is None:
+        ws = workspace(MD_FN_PROTOCOL, m, sysd.N, sysd.n, dmax, h.M, h.max_deg, x0.device)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=x0.device)
+    x = torch.empty((2, m, dmax + 1, sysd.n), dtype=torch.float64, device=x0.device)
+    iters = torch.empty(deg.size, dtype=torch.int32, device=x0.device)
+    norms = torch.empty((m, deg.size), dtype=torch.float64, device=x0.device)
+    _check(lib().md_newton_protocol(m, ctypes.byref(sysd.desc), _ptr(x0), int(deg.size),
+                                    deg.ctypes.data_as(ctypes.c_void_p),
+                                    mit.ctypes.data_as(ctypes.c_void_p), int(min_steps),
+                                    float(tol),
+                                    float(diverge), _ptr(x), _ptr(iters, torch.int32),
+                                    _ptr(norms), _ptr(ws, torch.uint8), ws.numel(),
+                                    _ptr(status, torch.int32), _stream(stream)),
+           "md_newton_protocol")
+    return x, iters, norms, status
 
 
 MD_NOALLOC_SCRATCH_BYTES = 32 << 20

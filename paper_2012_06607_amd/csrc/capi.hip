@@ -58,6 +58,7 @@ extern "C" size_t md_workspace_bytes(int fn, int m, int N, int n, int d, int M, 
     case MD_FN_NEWTON: return mds::NewtonLayout(m, N, n, d, M, max_deg).bytes;
     case MD_FN_ADJOINT: return mds::AdjointLayout(m, N, n, d, M, max_deg, false).bytes;
     case MD_FN_ADJOINT_STORE: return mds::AdjointLayout(m, N, n, d, M, max_deg, true).bytes;
+    case MD_FN_PROTOCOL: return mds::ProtocolLayout(m, N, n, d, M, max_deg).bytes;
     default: return 0;
   }
 }

@@ -45,6 +45,13 @@ int dispatch_m(int m, F &&f) {
 
 constexpr int WAVE = 64;
 
+// A gate word in device memory: kernels of a step enqueued ahead of time
+// return at once while it is zero (the Newton protocol switches a converged
+// degree's remaining steps off this way).  NULL: always open.
+__device__ __forceinline__ bool gate_closed(const int32_t *gate) {
+  return gate && *gate == 0;
+}
+
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
 
 template <int M>

@@ -17,6 +17,7 @@ namespace mds {
 
 template <int M>
 __global__ void __launch_bounds__(256) k_eval_terms(EvalArgs a) {
+  if (gate_closed(a.gate)) return;
   const int d = a.d;
   const int P = pairs_of(d);
   const int T = blockDim.x / P;
@@ -115,12 +116,14 @@ __global__ void __launch_bounds__(256) k_eval_terms(EvalArgs a) {
 template <int M>
 __global__ void __launch_bounds__(64) k_eval_terms_wave(EvalArgs a, int r) {
   extern __shared__ double lds_raw[];
+  if (gate_closed(a.gate)) return;
   eval_term_wave<M>(a, blockIdx.x, r, reinterpret_cast<mdc<M> *>(lds_raw),
                     [] { __syncthreads(); });
 }
 
 template <int M>
 __global__ void __launch_bounds__(256) k_eval_accumulate(EvalArgs a) {
+  if (gate_closed(a.gate)) return;
   const long total = long(a.N) * (a.n + 1) * (a.d + 1);
   for (long g = blockIdx.x * long(blockDim.x) + threadIdx.x; g < total;
        g += long(gridDim.x) * blockDim.x)
@@ -128,7 +131,8 @@ __global__ void __launch_bounds__(256) k_eval_accumulate(EvalArgs a) {
 }
 
 int eval_diff_enqueue(int m, int d, const md_system &sys, const double *x, double *f, double *A,
-                      void *ws, size_t ws_bytes, hipStream_t s, double *mono) {
+                      void *ws, size_t ws_bytes, hipStream_t s, double *mono,
+                      const int32_t *gate) {
   if (d < 0) return fail(MD_EINVAL, "md_poly_eval_diff: d=%d < 0", d);
   if (sys.N < 1 || sys.n < 1 || sys.M < 0 || sys.dc < 0 || sys.max_deg < 0)
     return fail(MD_ESHAPE, "md_poly_eval_diff: bad system sizes N=%d n=%d M=%d dc=%d max_deg=%d",
@@ -146,6 +150,7 @@ int eval_diff_enqueue(int m, int d, const md_system &sys, const double *x, doubl
   EvalArgs a{d, sys.N, sys.n, sys.M, sys.dc, sys.max_deg, lay.S, sys.eq_ptr, sys.term_ptr,
              sys.factors, sys.coef, x, static_cast<double *>(ws), lay.E, f, A, lay};
   a.mono = mono;
+  a.gate = gate;
   return dispatch_m(m, [&](auto Mc) {
     constexpr int Mm = decltype(Mc)::value;
     if (sys.M > 0) {

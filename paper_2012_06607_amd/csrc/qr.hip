@@ -18,15 +18,16 @@ __global__ void __launch_bounds__(qr_threads<M>()) k_qr(int N, int n, int seg,
                                                        double *__restrict__ QR,
                                                        double *__restrict__ vdiag,
                                                        double *__restrict__ beta,
-                                                       int32_t *status) {
+                                                       int32_t *status, const int32_t *gate) {
   __shared__ QrShared<M> sh;
+  if (gate_closed(gate)) return;
   int st = 0;
   qr_wg<M, RPL>(sh, N, n, seg, A0, A0E, QR, vdiag, beta, st);
   if (threadIdx.x == 0 && st && status) atomicOr(status, st);
 }
 
 int qr_enqueue(int m, int N, int n, const double *A0, long A0E, double *QR, double *vdiag,
-               double *beta, int32_t *status, hipStream_t s) {
+               double *beta, int32_t *status, hipStream_t s, const int32_t *gate) {
   if (n < 1 || N < n) return fail(MD_ESHAPE, "md_qr: need N >= n >= 1 (N=%d n=%d)", N, n);
   if (N > 256) return fail(MD_ESHAPE, "md_qr: N=%d above 256", N);
   if (!A0 || !QR || !vdiag || !beta) return fail(MD_ENULL, "md_qr: null pointer");
@@ -35,9 +36,9 @@ int qr_enqueue(int m, int N, int n, const double *A0, long A0E, double *QR, doub
     const int seg = N >= WAVE ? WAVE : pow2_at_least(N);
     const int rpl = (N + seg - 1) / seg;
     const dim3 blk(qr_threads<Mm>());
-    if (rpl == 1) k_qr<Mm, 1><<<dim3(1), blk, 0, s>>>(N, n, seg, A0, A0E, QR, vdiag, beta, status);
-    else if (rpl == 2) k_qr<Mm, 2><<<dim3(1), blk, 0, s>>>(N, n, seg, A0, A0E, QR, vdiag, beta, status);
-    else k_qr<Mm, 4><<<dim3(1), blk, 0, s>>>(N, n, seg, A0, A0E, QR, vdiag, beta, status);
+    if (rpl == 1) k_qr<Mm, 1><<<dim3(1), blk, 0, s>>>(N, n, seg, A0, A0E, QR, vdiag, beta, status, gate);
+    else if (rpl == 2) k_qr<Mm, 2><<<dim3(1), blk, 0, s>>>(N, n, seg, A0, A0E, QR, vdiag, beta, status, gate);
+    else k_qr<Mm, 4><<<dim3(1), blk, 0, s>>>(N, n, seg, A0, A0E, QR, vdiag, beta, status, gate);
     return check_launch("md_qr");
   });
 }

@@ -514,7 +514,9 @@ struct EvalArgs {
   double *f, *A;
   EvalLayout lay;
   double *mono = nullptr;  // when set: the monomial series x^a of each term, planes (2, m, Mt, d+1)
+  const int32_t *gate = nullptr;  // when set and *gate == 0, the kernels return at once
 };
+
 
 // LDS series of one term: its factor series, its coefficient series, the
 // forward products P_2..P_D, backward Q_2..Q_{D-1}, cross C_2..C_{D-1}

@@ -367,3 +367,71 @@ def test_least_squares_newton_on_a_consistent_overdetermined_system(m):
     xs, _, _ = oracle.newton(sysm, I.series_start(x0, d), 6)
     e = rel_err_per_k(x, mp_array(xs))
     assert np.all(e <= tol(m, 12)), e
+
+
+# ----------------------------------------------------------------------------
+# the protocol of Section 6 over increasing truncation degrees
+
+
+@pytest.mark.parametrize("m", (2, 4, 8))
+def test_protocol_iteration_counts_on_sqrt_series(m):
+    """x^2 - (1 + t) = 0 from x = 1: Newton on series doubles the number of
+    correct coefficients per step (t-adic quadratic convergence), and the
+    coefficients binom(1/2, k) are dyadic, so after ceil(log2(d+1)) steps
+    the series is exact and the next update is exactly zero.  Each degree
+    therefore stops after ceil(log2(d+1)) + 1 steps (Section 6's counts at
+    degrees 8 and 16 in penta, octo and deca double are 5 and 6, the same
+    numbers), with the exact series."""
+    degrees = (4, 8, 16)
+    sysm, x = I.sqrt_system(m, 16)
+    xo, iters, norms, st = oracle.newton_protocol(sysm, x[:, :, 0, :], degrees, (8, 8, 8),
+                                                  1e-32, 1.0)
+    assert st == 0
+    assert iters == [math.ceil(math.log2(d + 1)) + 1 for d in degrees] == [4, 5, 6]
+    assert not norms.any()
+    c = Fraction(1)
+    for k in range(17):
+        assert fval(xo[0, :, k, 0]) == c
+        c = c * (Fraction(1, 2) - k) / (k + 1)
+
+
+def test_protocol_stops_at_the_step_limit_and_after_divergence():
+    """A random double-double system: its updates stay above 1e-32 (the
+    double-double rounding level), so every degree takes its full 8, 8,
+    12, 16 steps (as quad double does in Section 6 at degree 8); with a
+    divergence bound below what degree 8 ends with, the later degrees are
+    not done and the status says so."""
+    m = 2
+    sysm, x0 = I.newton_system((922, 0), 6, m)
+    x, iters, norms, st = oracle.newton_protocol(sysm, x0, (8, 16, 24, 32), (8, 8, 12, 16),
+                                                 1e-32, 1.0)
+    assert st == 0 and iters == [8, 8, 12, 16]
+    assert np.all(norms[0] > 1e-32) and np.all(norms[0] < 1.0)
+    # the last degree's series is 16 plain Newton steps from x0 at degree 32
+    xs, nl, _ = oracle.newton(sysm, I.series_start(x0, 32), 16)
+    assert np.array_equal(x, xs) and np.array_equal(norms[:, 3], nl[-1][:, 0])
+    bound = float(norms[0, 0]) / 2
+    x, iters, norms2, st = oracle.newton_protocol(sysm, x0, (8, 16, 24, 32), (8, 8, 12, 16),
+                                                  1e-32, bound)
+    assert st == oracle.ST_DIVERGED and iters == [8, 0, 0, 0]
+    assert np.array_equal(norms2[:, 0], norms[:, 0]) and not norms2[:, 1:].any()
+    xs, _, _ = oracle.newton(sysm, I.series_start(x0, 8), 8)
+    assert np.array_equal(x[:, :, :9], xs) and not x[:, :, 9:].any()
+
+
+def test_protocol_quad_double_converges_in_few_steps():
+    """In quad double the same kind of system converges: each degree stops
+    at the first step whose update to the last coefficient is at most 1e-32,
+    after the ceil(log2(d+1)) steps that reach that coefficient."""
+    m = 4
+    sysm, x0 = I.newton_system((922, 1), 6, m)
+    degrees = (8, 16, 24, 32)
+    x, iters, norms, st = oracle.newton_protocol(sysm, x0, degrees, (8, 8, 12, 16), 1e-32, 1.0)
+    assert st == 0
+    for j, d in enumerate(degrees):
+        xs, nl, _ = oracle.newton(sysm, I.series_start(x0, d), iters[j])
+        vals = [float(fval(v[:, 0])) for v in nl]
+        # the stop is at the first step from the second on at or below 1e-32
+        assert vals[-1] <= 1e-32 and all(v > 1e-32 for v in vals[1:-1])
+        assert iters[j] >= math.ceil(math.log2(d + 1))
+    assert np.array_equal(x, xs)
