@@ -782,7 +782,10 @@ int orc_series_solve(int m, int N, int n, int d, const double *QR, const double 
     cmd_t *r = malloc(sizeof(cmd_t) * (size_t)bE);
     cmd_t *y = malloc(sizeof(cmd_t) * (size_t)N);
     cmd_t *z = malloc(sizeof(cmd_t) * (size_t)n);
-    if (!qr || !vd || !bet || !r || !y || !z) return 3;
+    if (!qr || !vd || !bet || !r || !y || !z) {
+        free(qr); free(vd); free(bet); free(r); free(y); free(z);
+        return 3;
+    }
     for (int64_t e = 0; e < E; ++e) qr[e] = cload(m, QR, E, e);
     for (int j = 0; j < n; ++j) { vd[j] = cload(m, vdiag, n, j); bet[j] = rload(m, beta, n, j); }
     for (int64_t e = 0; e < bE; ++e) r[e] = cload(m, b, bE, e);
@@ -830,9 +833,15 @@ int orc_newton_step(int m, int d, int N, int n, int M, int dc, const int32_t *eq
     double *vd = malloc(sizeof(double) * (size_t)2 * m * n);
     double *bet = malloc(sizeof(double) * (size_t)m * n);
     double *dx = malloc(sizeof(double) * (size_t)2 * m * L * n);
-    if (!f || !A || !A0 || !QR || !vd || !bet || !dx) return 3;
+    if (!f || !A || !A0 || !QR || !vd || !bet || !dx) {
+        free(f); free(A); free(A0); free(QR); free(vd); free(bet); free(dx);
+        return 3;
+    }
     int rc = orc_eval_diff(m, d, N, n, M, dc, eq_ptr, term_ptr, factors, coef, x, f, A);
-    if (rc) return rc;
+    if (rc) {
+        free(f); free(A); free(A0); free(QR); free(vd); free(bet); free(dx);
+        return rc;
+    }
     for (size_t q = 0; q < fsz; ++q) f[q] = -f[q]; /* b = -f (exact) */
     int64_t AE = (int64_t)L * N * n, E0 = (int64_t)N * n;
     for (int p = 0; p < 2 * m; ++p)
@@ -913,10 +922,11 @@ int orc_newton_adjoint(int m, int d, int N, int n, int M, int dc, const int32_t 
     cmd_t *lam = malloc(sizeof(cmd_t) * (size_t)L * N);
     cmd_t *y = malloc(sizeof(cmd_t) * (size_t)N);
     cmd_t *ser = malloc(sizeof(cmd_t) * (size_t)L * 3);
+    int rc = 3;
     if (!f || !A || !A0 || !QR || !vdp || !betp || !qr || !vd || !bet || !rhs || !lam || !y || !ser)
-        return 3;
-    int rc = orc_eval_diff(m, d, N, n, M, dc, eq_ptr, term_ptr, factors, coef, x, f, A);
-    if (rc) return rc;
+        goto done;
+    rc = orc_eval_diff(m, d, N, n, M, dc, eq_ptr, term_ptr, factors, coef, x, f, A);
+    if (rc) goto done;
     int64_t AE = (int64_t)L * N * n, E0 = (int64_t)N * n, xE = (int64_t)L * n;
     for (int p = 0; p < 2 * m; ++p)
         memcpy(A0 + (size_t)p * E0, A + (size_t)p * AE, sizeof(double) * (size_t)E0);
@@ -978,7 +988,9 @@ int orc_newton_adjoint(int m, int d, int N, int n, int M, int dc, const int32_t 
                 }
             }
         }
+    rc = 0;
+done:
     free(f); free(A); free(A0); free(QR); free(vdp); free(betp); free(qr); free(vd); free(bet);
     free(rhs); free(lam); free(y); free(ser);
-    return 0;
+    return rc;
 }
