@@ -94,6 +94,30 @@ typedef struct md_system {
 int md_series_convolve(int m, int d, int64_t count, const double *x, const double *y, double *z,
                        void *stream);
 
+/* Series division (Section 3: a series with a nonzero constant term has
+ * an inverse, and series divide like numbers): z[c] = x[c] / y[c] mod
+ * t^{d+1} for count independent series, planes (2, m, count, d+1).
+ * z_0 = x_0 / y_0 and z_k = (x_k - (y_1 z_{k-1} + ... + y_k z_0)) / y_0,
+ * the products added in increasing order (the same operations as the
+ * oracle, so the bits agree).  A zero y_0 sets MD_ST_SINGULAR in *status
+ * (may be NULL) and the quotient is undefined.  z must not overlap x or y.
+ * Errors: MD_EINVAL (bad m, d < 0, count < 0), MD_ENULL. */
+int md_series_divide(int m, int d, int64_t count, const double *x, const double *y, double *z,
+                     int32_t *status, void *stream);
+
+/* [L/M] Pade approximants of count series (Section 3: computed series give
+ * rational approximations): c planes (2, m, count, L+M+1) -> p planes
+ * (2, m, count, L+1) and q planes (2, m, count, M+1) with q_0 = 1 and
+ * q(t) c(t) - p(t) = O(t^{L+M+1}).  The denominator solves the M x M
+ * Toeplitz system sum_{j=1..M} c_{L+i-j} q_j = -c_{L+i} (i = 1..M,
+ * c_k = 0 for k < 0) by the Householder QR and reflector solve of the
+ * Newton step; p_k = sum_{j=0..min(k,M)} q_j c_{k-j}.  One workgroup per
+ * series; M <= 64.  A singular system sets MD_ST_SINGULAR.
+ * Workspace (M > 0): md_workspace_bytes(MD_FN_PADE, m, M, L, 0, count, 0).
+ * Errors: MD_EINVAL, MD_ESHAPE (M > 64), MD_ENULL, MD_EWORKSPACE. */
+int md_series_pade(int m, int L, int M, int64_t count, const double *c, double *p, double *q,
+                   void *ws, size_t ws_bytes, int32_t *status, void *stream);
+
 /* Evaluation and reverse-mode differentiation of a system at a series point
  * (Section 4, algorithmic differentiation: all n partial derivatives for a
  * small multiple of the cost of the value).  For each term with factor list
@@ -242,7 +266,9 @@ enum {
   MD_FN_NEWTON = 3,
   MD_FN_ADJOINT = 4,
   MD_FN_ADJOINT_STORE = 5,
-  MD_FN_PROTOCOL = 6 /* md_newton_protocol; d is the largest degree */
+  MD_FN_PROTOCOL = 6, /* md_newton_protocol; d is the largest degree */
+  MD_FN_PADE = 7      /* md_series_pade: N = denominator degree, n = numerator degree,
+                         M = number of series (d and max_deg unused) */
 };
 size_t md_workspace_bytes(int fn, int m, int N, int n, int d, int M, int max_deg);
 

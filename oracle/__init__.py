@@ -61,6 +61,7 @@ def lib() -> ctypes.CDLL:
             L.orc_elementwise.argtypes = [i32, i32, i64, P, P, P]
             L.orc_norm2.argtypes = [i32, i64, P, P]
             L.orc_convolve.argtypes = [i32, i32, i64, P, P, P]
+            L.orc_series_divide.argtypes = [i32, i32, i64, P, P, P, P]
             L.orc_eval_diff.argtypes = [i32, i32, i32, i32, i32, i32, P, P, P, P, P, P, P]
             L.orc_qr.argtypes = [i32, i32, i32, P, P, P, P, P]
             L.orc_series_solve.argtypes = [i32, i32, i32, i32, P, P, P, P, P, P, P]
@@ -127,6 +128,56 @@ def convolve(x: np.ndarray, y: np.ndarray) -> np.ndarray:
     z = np.zeros_like(x)
     _check(lib().orc_convolve(m, L - 1, count, _p(x), _p(y), _p(z)), "convolve")
     return z
+
+
+def series_divide(x: np.ndarray, y: np.ndarray):
+    """z = x / y mod t^{d+1} per series, planes (2, m, count, d+1); returns
+    (z, status) with ST_SINGULAR when some y_0 is zero."""
+    x, y = _c(x), _c(y)
+    assert x.shape == y.shape
+    _, m, count, L = x.shape
+    z = np.zeros_like(x)
+    st = np.zeros(1, dtype=np.int32)
+    _check(lib().orc_series_divide(m, L - 1, count, _p(x), _p(y), _p(z), _p(st)), "series_divide")
+    return z, int(st[0])
+
+
+def pade(c: np.ndarray, L: int, M: int):
+    """[L/M] Pade approximants p(t)/q(t) of the series c (planes
+    (2, m, count, L+M+1)), the rational approximations of Section 3 built
+    from a computed series: q(t) = 1 + q_1 t + ... + q_M t^M and p(t) of
+    degree L with q(t) c(t) - p(t) = O(t^{L+M+1}).  The coefficients of
+    t^{L+1} .. t^{L+M} of q c vanish:
+        sum_{j=1..M} c_{L+i-j} q_j = -c_{L+i},   i = 1..M  (c_k = 0, k < 0),
+    an M x M Toeplitz system, solved by Householder QR (qr and
+    series_solve at degree 0); then p_k = sum_{j=0..min(k,M)} q_j c_{k-j},
+    k = 0..L (a truncated series product).  Returns (p planes
+    (2, m, count, L+1), q planes (2, m, count, M+1), status)."""
+    c = _c(c)
+    _, m, count, K = c.shape
+    assert K == L + M + 1 and L >= 0 and M >= 0
+    p = np.zeros((2, m, count, L + 1))
+    q = np.zeros((2, m, count, M + 1))
+    status = 0
+    for s in range(count):
+        q[0, 0, s, 0] = 1.0
+        if M > 0:
+            T = np.zeros((2, m, M, M))
+            rhs = np.zeros((2, m, M))
+            for i in range(1, M + 1):
+                for j in range(1, M + 1):
+                    if L + i - j >= 0:
+                        T[:, :, i - 1, j - 1] = c[:, :, s, L + i - j]
+                rhs[:, :, i - 1] = -c[:, :, s, L + i]
+            QR, vd, beta, st1 = qr(T)
+            qs, st2 = series_solve(QR, vd, beta, T[:, :, None], rhs[:, :, None])
+            q[:, :, s, 1:] = qs[:, :, 0, :]
+            status |= st1 | st2
+        qq = np.zeros((2, m, 1, L + 1))
+        top = min(L, M)
+        qq[:, :, 0, :top + 1] = q[:, :, s, :top + 1]
+        p[:, :, s, :] = convolve(qq, c[:, :, s:s + 1, :L + 1])[:, :, 0, :]
+    return p, q, status
 
 
 def _sys_args(sysm):

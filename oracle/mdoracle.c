@@ -544,6 +544,43 @@ int orc_convolve(int m, int d, int64_t count, const double *x, const double *y, 
     return 0;
 }
 
+/*
+ * z[c] = x[c] / y[c] mod t^{d+1} (Section 3: a series with a nonzero
+ * constant term has an inverse, and series divide like numbers).  From
+ * x(t) = y(t) z(t): z_0 = x_0 / y_0 and, for k = 1..d,
+ * z_k = (x_k - (y_1 z_{k-1} + y_2 z_{k-2} + ... + y_k z_0)) / y_0,
+ * the products added in increasing i.  A zero y_0 sets ST_SINGULAR (the
+ * quotient is then not defined; its coefficients are whatever the
+ * divisions give).  Planes (2, m, count, d+1).
+ */
+int orc_series_divide(int m, int d, int64_t count, const double *x, const double *y, double *z,
+                      int32_t *status)
+{
+    if (!valid_m(m) || d < 0 || count < 0) return 1;
+    int64_t E = count * (d + 1);
+    cmd_t *zc = malloc(sizeof(cmd_t) * (size_t)(d + 1));
+    if (!zc) return 3;
+    int32_t st = 0;
+    for (int64_t c = 0; c < count; ++c) {
+        int64_t b = c * (d + 1);
+        cmd_t y0 = cload(m, y, E, b);
+        if (y0.re.v[0] == 0.0 && y0.im.v[0] == 0.0) st |= 1;
+        for (int k = 0; k <= d; ++k) {
+            cmd_t r = cload(m, x, E, b + k);
+            if (k > 0) {
+                cmd_t s = c_mul(m, cload(m, y, E, b + 1), zc[k - 1]);
+                for (int i = 2; i <= k; ++i) s = c_add(m, s, c_mul(m, cload(m, y, E, b + i), zc[k - i]));
+                r = c_sub(m, r, s);
+            }
+            zc[k] = c_div(m, r, y0);
+            cstore(m, z, E, b + k, zc[k]);
+        }
+    }
+    free(zc);
+    if (status) *status = st;
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* evaluation and reverse-mode differentiation (Section 4)                    */
 

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_PKG, "libmdseries.so")
 
 MD_FN_EVAL, MD_FN_SOLVE, MD_FN_NEWTON, MD_FN_ADJOINT, MD_FN_ADJOINT_STORE = 1, 2, 3, 4, 5
 MD_FN_PROTOCOL = 6
+MD_FN_PADE = 7
 MD_PROTOCOL_MAX_DEGREES = 16
 MD_ST_SINGULAR, MD_ST_NONFINITE, MD_ST_BADPATH, MD_ST_GANG, MD_ST_NOTRUN = 1, 2, 4, 8, 16
 MD_ST_DIVERGED = 32
@@ -58,6 +59,8 @@ def lib() -> ctypes.CDLL:
         L.md_series_solve.argtypes = [i32, i32, i32, i32, P, P, P, P, P, P, P, sz, P, P]
         L.md_newton_step.argtypes = [i32, i32, ctypes.POINTER(md_system), P, P, P, sz, P, P]
         L.md_newton_step_noalloc.argtypes = [i32, i32, ctypes.POINTER(md_system), P, P, P, P]
+        L.md_series_divide.argtypes = [i32, i32, i64, P, P, P, P, P]
+        L.md_series_pade.argtypes = [i32, i32, i32, i64, P, P, P, P, sz, P, P]
         L.md_newton_protocol.argtypes = [i32, ctypes.POINTER(md_system), P, i32, P, P, i32,
                                          ctypes.c_double, ctypes.c_double, P, P, P, P, sz, P, P]
         L.md_newton_adjoint.argtypes = [i32, i32, ctypes.POINTER(md_system), P, P, i32, P, P, sz,
@@ -198,6 +201,47 @@ def md_series_convolve(x: torch.Tensor, y: torch.Tensor, z: torch.Tensor | None 
     _check(lib().md_series_convolve(m, L - 1, count, _ptr(x), _ptr(y), _ptr(z), _stream(stream)),
            "md_series_convolve")
     return z
+
+
+def md_series_divide(x: torch.Tensor, y: torch.Tensor, status=None, stream=None):
+    """z = x / y mod t^{d+1} per series (planes (2, m, count, d+1)); returns
+    (z, status) with MD_ST_SINGULAR set when some y_0 is zero."""
+    m = _limbs(x)
+    if tuple(x.shape) != tuple(y.shape) or x.dim() != 4:
+        raise MdError("md_series_divide: x and y must be equal planes (2, m, count, d+1)")
+    _, _, count, L = x.shape
+    z = torch.empty_like(x)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=x.device)
+    _check(lib().md_series_divide(m, L - 1, count, _ptr(x), _ptr(y), _ptr(z),
+                                  _ptr(status, torch.int32), _stream(stream)), "md_series_divide")
+    return z, status
+
+
+def md_series_pade(c: torch.Tensor, L: int, M: int, status=None, stream=None):
+    """[L/M] Pade approximants p/q of the series c (planes (2, m, count,
+    L+M+1)); returns (p (2, m, count, L+1), q (2, m, count, M+1), status)."""
+    m = _limbs(c)
+    if c.dim() != 4 or c.shape[3] != L + M + 1:
+        raise MdError("md_series_pade: c must be planes (2, m, count, L+M+1)")
+    count = c.shape[2]
+    p = torch.empty((2, m, count, L + 1), dtype=torch.float64, device=c.device)
+    q = torch.empty((2, m, count, M + 1), dtype=torch.float64, device=c.device)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=c.device)
+    ws = None
+    if M > 0 and count > 0:
+        nbytes = lib().md_workspace_bytes(MD_FN_PADE, m, M, L, 0, count, 0)
+        if nbytes == 0:
+            raise MdError("md_series_pade: unsupported sizes")
+        raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=c.device)
+        off = (-raw.data_ptr()) % 256
+        ws = raw[off:off + nbytes]
+    _check(lib().md_series_pade(m, L, M, count, _ptr(c), _ptr(p), _ptr(q),
+                                _ptr(ws, torch.uint8) if ws is not None else None,
+                                ws.numel() if ws is not None else 0, _ptr(status, torch.int32),
+                                _stream(stream)), "md_series_pade")
+    return p, q, status
 
 
 def md_poly_eval_diff(sysd: DeviceSystem, x: torch.Tensor, f=None, A=None, ws=None,

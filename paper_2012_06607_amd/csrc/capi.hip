@@ -51,6 +51,10 @@ extern "C" size_t md_device_lds_bytes(void) { return mds::lds_limit(); }
 extern "C" const char *md_last_error(void) { return mds::g_err; }
 
 extern "C" size_t md_workspace_bytes(int fn, int m, int N, int n, int d, int M, int max_deg) {
+  if (fn == MD_FN_PADE) {  // N: denominator degree, n: numerator degree, M: series count
+    if (!mds::valid_m(m) || N < 0 || N > 64 || n < 0 || M < 0) return 0;
+    return mds::PadeLayout(m, N, M).bytes;
+  }
   if (!mds::valid_m(m) || N < 1 || n < 1 || d < 0 || M < 0 || max_deg < 0) return 0;
   switch (fn) {
     case MD_FN_EVAL: return mds::EvalLayout(m, N, n, d, M, max_deg).bytes;
@@ -59,6 +63,7 @@ extern "C" size_t md_workspace_bytes(int fn, int m, int N, int n, int d, int M, 
     case MD_FN_ADJOINT: return mds::AdjointLayout(m, N, n, d, M, max_deg, false).bytes;
     case MD_FN_ADJOINT_STORE: return mds::AdjointLayout(m, N, n, d, M, max_deg, true).bytes;
     case MD_FN_PROTOCOL: return mds::ProtocolLayout(m, N, n, d, M, max_deg).bytes;
+    case MD_FN_PADE: return mds::PadeLayout(m, N, M).bytes;
     default: return 0;
   }
 }

@@ -101,4 +101,22 @@ struct ProtocolLayout {
   }
 };
 
+// Pade approximants: per series the M x M Toeplitz matrix (factored in
+// place), the reflector heads, beta, 1/R_ii, the right-hand side and the
+// solution.
+struct PadeLayout {
+  size_t off_QR, off_vd, off_beta, off_invd, off_rhs, off_sol, per_series, bytes;
+  __host__ __device__ PadeLayout(int m, int Md, long count) {
+    const size_t Mq = size_t(Md > 0 ? Md : 1);
+    off_QR = 0;
+    off_vd = align256(sizeof(double) * 2 * m * Mq * Mq);
+    off_beta = off_vd + align256(sizeof(double) * 2 * m * Mq);
+    off_invd = off_beta + align256(sizeof(double) * m * Mq);
+    off_rhs = off_invd + align256(sizeof(double) * 2 * m * Mq);
+    off_sol = off_rhs + align256(sizeof(double) * 2 * m * Mq);
+    per_series = off_sol + align256(sizeof(double) * 2 * m * Mq);
+    bytes = per_series * size_t(count > 0 ? count : 1);
+  }
+};
+
 }  // namespace mds

@@ -441,6 +441,78 @@ __device__ __forceinline__ void pinv_column(bool live, int c, int N, int n, int 
   }
 }
 
+// x = R^{-1} (Q^H b)_{0:n} for one right-hand side b (N entries) by one
+// segment: b's rows go to the lanes as in pinv_column, the n reflectors are
+// applied in order, then the back substitution with the row owner
+// multiplying by 1/R_ii and broadcasting.  x: n entries (plane stride n).
+// `live` false: the segment only joins the shuffles.
+template <int M, int RPL>
+__device__ __forceinline__ void qr_solve_vector(bool live, int N, int n, int seg,
+                                                const double *__restrict__ QR,
+                                                const double *__restrict__ vdiag,
+                                                const double *__restrict__ beta,
+                                                const double *__restrict__ invd,
+                                                const double *__restrict__ b,
+                                                double *__restrict__ x) {
+  const long E = long(N) * n;
+  const int lane = lane_id();
+  const int lis = lane & (seg - 1);
+  mdc<M> g[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int i = lis + r * seg;
+    g[r] = (live && i < N) ? cload<M>(b, N, i) : c_zero<M>();
+  }
+  for (int j = 0; j < n; ++j) {
+    const mdc<M> v0 = cload<M>(vdiag, n, j);
+    const mdr<M> bet = rload<M>(beta, n, j);
+    mdc<M> vi[RPL];
+    mdc<M> w = c_zero<M>();
+    bool first = true;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int i = lis + r * seg;
+      vi[r] = c_zero<M>();
+      if (live && i >= j && i < N) {
+        vi[r] = i == j ? v0 : cload<M>(QR, E, long(i) * n + j);
+        const mdc<M> t = c_mul<M>(c_conj<M>(vi[r]), g[r]);
+        w = first ? t : c_add<M>(w, t);
+        first = false;
+      }
+    }
+    w = seg_reduce_c<M>(w, seg);
+    w = shfl_c<M>(w, lane & ~(seg - 1));
+    const mdc<M> bw = c_mulr<M>(w, bet);
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int i = lis + r * seg;
+      if (live && i >= j && i < N) g[r] = c_sub<M>(g[r], c_mul<M>(bw, vi[r]));
+    }
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    const int owner = i & (seg - 1), ro = i / seg;
+    mdc<M> xi = c_zero<M>();
+#pragma unroll
+    for (int r = 0; r < RPL; ++r)
+      if (live && r == ro && lis == owner) xi = c_mul<M>(g[r], cload<M>(invd, n, i));
+    xi = shfl_c<M>(xi, (lane & ~(seg - 1)) + owner);
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int l = lis + r * seg;
+      if (!live) continue;
+      if (l == i) g[r] = xi;
+      else if (l < i) g[r] = c_sub<M>(g[r], c_mul<M>(cload<M>(QR, E, long(l) * n + i), xi));
+    }
+  }
+  if (live) {
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int i = lis + r * seg;
+      if (i < n) cstore<M>(x, n, i, g[r]);
+    }
+  }
+}
+
 // Lanes per dot product of the staggered stages (length len).  The
 // single-path kernels take one product per lane (shortest chain); the
 // batched kernel, where a workgroup has many rows to do, lets each lane sum
