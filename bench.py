@@ -98,6 +98,14 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint measurement (32 unknowns, d = 16, quad double)")
     ap.add_argument("--adj-reps", type=int, default=20)
+    ap.add_argument("--efficiency", action="store_true",
+                    help="instead of the headline: the efficiency study of Section 7 (64 "
+                         "polynomials with 64 monomials each, degrees 8, 16, 32, seven "
+                         "precisions), one Newton step of one system on a gang of G = 1, 2, "
+                         "4, 8, 16, 32 workgroups; prints one JSON line")
+    ap.add_argument("--eff-reps", type=int, default=3)
+    ap.add_argument("--eff-precisions", type=str, default="1,2,3,4,5,8,10")
+    ap.add_argument("--eff-degrees", type=str, default="8,16,32")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="before timing, run one plain device copy of this many MiB (a "
                          "reference of known traffic for hardware byte counters)")
@@ -432,6 +440,67 @@ def adjoint_measure(args, B, OC) -> dict:
     }
 
 
+EFF_GANGS = (1, 2, 4, 8, 16, 32)
+
+
+def efficiency_study(args, B, OC) -> dict:
+    """Section 7's efficiency experiment on the GPU.  The paper runs one
+    Newton step of a random system of 64 polynomials with 64 monomials per
+    polynomial (power series truncated at degree 8, 16, 32; double, double
+    double, triple, quad, penta, octo and deca double) on p worker threads
+    taking jobs from a queue, and reports efficiency = speedup / p for
+    p = 2, 4, 8, 16, 32, 40.  Here the workers are the workgroups of a gang
+    (one workgroup per CU) splitting the path's jobs (terms, Jacobian rows,
+    columns of R^{-1} Q^H, right-hand-side updates) in the persistent
+    kernel: efficiency(G) = T(1) / (G T(G)) for G = 1 .. 32 workgroups.
+    Each time is the mean of `reps` launches of one Newton step (HIP events
+    on the launch stream), inputs restored outside the timed region."""
+    import numpy as np
+    import torch
+    from paper_2012_06607_amd import inputs as I
+    stream = torch.cuda.current_stream()
+    ms_list = [int(v) for v in args.eff_precisions.split(",")]
+    ds = [int(v) for v in args.eff_degrees.split(",")]
+    rows = []
+    for m in ms_list:
+        sysm, x0 = I.newton_system((7, 64, m), 64, m, terms=64, max_deg=3)
+        for d in ds:
+            x = I.series_start(x0, d)
+            ops = OC.newton_step(sysm, d, m).table_ops(m)
+            batch = B.BatchedPaths([(sysm, x)])
+            block = 512 if m <= 4 else 256
+            row = {"m": m, "d": d, "table_ops": ops, "ms": {}, "status": 0}
+            for G in EFF_GANGS:
+                batch.set_schedule(gangs=np.array([G]))
+                times = []
+                for rep in range(args.eff_reps + 1):
+                    batch.restore()
+                    torch.cuda.synchronize()
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    B.md_newton_batch(batch, 1, grid=G, block=block, stream=stream)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    if rep:
+                        times.append(e0.elapsed_time(e1))
+                row["status"] |= int(batch.status.max().item())
+                row["ms"][G] = float(np.mean(times))
+            t1 = row["ms"][1]
+            row["speedup"] = {G: t1 / row["ms"][G] for G in EFF_GANGS}
+            row["efficiency"] = {G: t1 / (G * row["ms"][G]) for G in EFF_GANGS}
+            row["pct_peak_one_cu"] = ops / (t1 * 1e-3) / (78.6e12 / 256) * 100
+            print(json.dumps({"efficiency_row": {k: row[k] for k in ("m", "d", "ms", "efficiency",
+                                                                    "status")}}), flush=True)
+            rows.append(row)
+            del batch
+            torch.cuda.empty_cache()
+    return {"workload": "one Newton step of one random system: 64 polynomials in 64 "
+                        "unknowns, 64 monomials of degree <= 3 per polynomial plus a constant "
+                        "and a t-term, at a unit start point",
+            "workers": "workgroups of one gang (one per CU), G = " + ", ".join(map(str, EFF_GANGS)),
+            "rows": rows}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -442,6 +511,15 @@ def main():
     if torch.cuda.device_count() < 1:   # counts devices without initialising one
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.efficiency:
+        from paper_2012_06607_amd import binding as B
+        from paper_2012_06607_amd import opcount as OC
+        if not torch.cuda.is_available():
+            print("bench.py needs a GPU", file=sys.stderr)
+            sys.exit(1)
+        B.lib()
+        print(json.dumps({"efficiency_study": efficiency_study(args, B, OC)}), flush=True)
+        return
     paths = make_paths(args.paths)
     cpu = None
     if not args.no_cpu_baseline:

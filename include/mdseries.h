@@ -304,10 +304,13 @@ int md_norm2(int m, int64_t count, const double *x, double *out, void *stream);
  * and gang split gives the same bits.
  *
  * One path, in a device array of md_path (all offsets are element offsets):
- *   m in 1..4 (the batched kernel carries double to quad double),
- *   1 <= n <= N <= 64, d >= 0 (md_newton_batch refuses a batch whose max_m
- *   or max_N is outside these ranges; a path table that breaks them anyway
- *   gets MD_ST_BADPATH for that path, which is then not run);
+ *   m in 1..4 (double to quad double) or in {5, 8, 10} (penta, octo and
+ *   deca double, a kernel of its own with 256-thread workgroups): a launch
+ *   takes the kernel of its max_m, and a path of the other class in it gets
+ *   MD_ST_BADPATH; 1 <= n <= N <= 64, d >= 0 (md_newton_batch refuses a
+ *   batch whose max_m or max_N is outside these ranges; a path table that
+ *   breaks them anyway gets MD_ST_BADPATH for that path, which is then not
+ *   run);
  *   eq_ptr, term_ptr, factors: offsets into `ints` (int32) of the path's
  *   system structure, laid out as in md_system (M terms, max_deg factors at
  *   most, coefficient degree dc);
@@ -343,14 +346,17 @@ size_t md_batch_lds_bytes(int max_m, int max_d, int max_deg, int eval_waves);
  * device int32[npaths], MD_ST_* bits per path (cleared by the caller; the
  * call sets MD_ST_NOTRUN first and clears it when the path is done).
  * max_m, max_N, max_d, max_deg: maxima over the paths (host values; max_m
- * and max_N must be at most 4 and 64, and max_d, max_deg size the LDS);
+ * in 1..4 or one of 5, 8, 10, max_N at most 64, and max_d, max_deg size
+ * the LDS);
  * grid: the number of persistent workgroups (each queue needs as many
  * resident workgroups on its die as its largest gang); block: threads per
- * workgroup, 256 or 512; eval_waves (1..block/64): waves per workgroup that
+ * workgroup, 256 or 512 (256 when max_m >= 5); eval_waves (1..block/64):
+ * waves per workgroup that
  * evaluate terms; path_clock (may be NULL): device int64[2*npaths],
  * receives for every path the device wall clock (md_wall_clock_hz ticks per
  * second) when its member 0 took it and when it finished.
- * Errors: MD_EINVAL (max_m outside 1..4 among others), MD_ENULL, MD_ESHAPE
+ * Errors: MD_EINVAL (max_m not in 1..4, 5, 8, 10; block 512 with max_m >= 5;
+ * among others), MD_ENULL, MD_ESHAPE
  * (max_N outside 1..64, or LDS above md_device_lds_bytes()), MD_EHIP. */
 int md_newton_batch(int npaths, const md_path *paths, int njobs, const int32_t *jobs, int nq,
                     const int32_t *qbegin, const int32_t *ints, double *reals, double *ws,

@@ -437,6 +437,12 @@ MD_PATH_DTYPE = np.dtype([("m", "<i4"), ("N", "<i4"), ("n", "<i4"), ("d", "<i4")
                           ("coef", "<i8"), ("x", "<i8"), ("dx_norm", "<i8"), ("ws", "<i8")])
 assert MD_PATH_DTYPE.itemsize == 88
 BATCH_MAX_M, BATCH_MAX_N = 4, 64
+BATCH_LO_M, BATCH_HI_M = (1, 2, 3, 4), (5, 8, 10)
+
+
+def sysm_class(m: int) -> bool:
+    """True for the penta to deca double kernel."""
+    return m in BATCH_HI_M
 
 
 class BatchedPaths:
@@ -459,10 +465,15 @@ class BatchedPaths:
             d = x.shape[2] - 1
             if x.shape != (2, m, d + 1, sysm.n):
                 raise MdError(f"path {p}: x must have shape (2, m, d+1, n)")
-            # the batched kernel carries double to quad double and at most 64
-            # equations (one lane per row of the QR and of R^{-1} Q^H segments)
-            if not 1 <= m <= BATCH_MAX_M:
-                raise MdError(f"path {p}: m={m} is not carried by the batched kernel (1..4)")
+            # the batched kernels carry double to quad double, or penta, octo
+            # and deca double (one launch holds one of the two classes), and
+            # at most 64 equations (one lane per row of the QR and of the
+            # R^{-1} Q^H segments)
+            if m not in BATCH_LO_M + BATCH_HI_M:
+                raise MdError(f"path {p}: m={m} is not carried by the batched kernels")
+            if (m in BATCH_HI_M) != (sysm_class(paths[0][0].m)):
+                raise MdError(f"path {p}: m={m} and m={paths[0][0].m} in one batch (double to "
+                              "quad double and penta to deca double run in separate launches)")
             if not 1 <= sysm.n <= sysm.N <= BATCH_MAX_N:
                 raise MdError(f"path {p}: needs 1 <= n <= N <= {BATCH_MAX_N} "
                               f"(n={sysm.n}, N={sysm.N})")
@@ -601,6 +612,11 @@ def md_newton_batch(batch: BatchedPaths, iters: int, grid: int | None = None,
     L.md_newton_batch.argtypes = [i32, P, i32, P, i32, P, P, P, P, i32, P, P, P, i32, i32, i32,
                                   i32, i32, i32, i32, P, P]
     L.md_newton_batch.restype = ctypes.c_int
+    if batch.max_m >= 5 and block != 256:
+        if block == 512 and eval_waves is None:
+            block = 256  # penta to deca double run 256-thread workgroups
+        else:
+            raise MdError("md_newton_batch: penta to deca double paths run with block=256")
     if eval_waves is None:
         eval_waves = block // 64
         while eval_waves > 1 and md_batch_lds_bytes(batch.max_m, batch.max_d, batch.max_deg,

@@ -1,0 +1,335 @@
+// Many independent solution paths in one persistent launch: the kernel.
+//
+// The paper's job queue (Section 5, Figure 1): all data is set up before
+// the workers start, each job reads shared inputs and writes its own
+// workspace, and a counter guarded by a lock hands out the next job.  Here
+// the workers are workgroups resident on the GPU, the counter is one device
+// atomic per queue, and a job is a whole path: `iters` Newton steps
+// (evaluation and differentiation, QR of A_0, R^{-1} Q^H, the staggered
+// solve, the update) run by that workgroup with barriers between the stages
+// (the paper's stage synchronisation by terminating tasks).  Jobs are taken
+// in the order the caller gives (longest first balances the load), and each
+// workgroup dispatches on its path's precision.
+//
+// A large path may be a gang of G workgroups (G members, one job each).
+// The members split the term evaluations, the Jacobian rows, the columns of
+// R^{-1} Q^H and the right-hand-side updates, and meet at gang barriers (a
+// counter in device memory, with device-scope release and acquire).  The QR
+// and the update of x run on member 0; every member computes the stage
+// products dx_k itself (the same bits), so a stage costs one gang barrier.
+// With one queue per accelerator die (queue q served by the workgroups on
+// die q) a gang's members share that die's L2.
+#pragma once
+
+#include "internal.hpp"
+#include "wg.hpp"
+
+namespace mds {
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// max over the workgroup of an exact selection (values are compared, the
+// bits of the largest are kept), through LDS
+template <int M>
+__device__ __forceinline__ mdr<M> wg_max(mdr<M> v, mdr<M> *sh) {
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    const mdr<M> t = shfl_down_r<M>(v, o);
+    if (lane_id() < o && md_less<M>(v, t)) v = t;
+  }
+  const int wave = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+  if (lane_id() == 0) sh[wave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int w = 1; w < nw; ++w)
+      if (md_less<M>(v, sh[w])) v = sh[w];
+  __syncthreads();
+  return v;
+}
+
+// Accelerator die (XCC) of the calling wave.
+__device__ __forceinline__ int xcc_id() {
+  unsigned v;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+  return int(v & 0xf);
+}
+
+// Gang barrier: every thread's memory operations complete, then member
+// thread 0 releases at device scope (the workgroup's stores become visible
+// to the other members), arrives on the counter and waits for all G
+// arrivals of this round (bounded: a round that never completes sets
+// MD_ST_GANG, and after that the workgroup waits no more), then acquires at
+// device scope (stale cache lines dropped) before the workgroup goes on.
+__device__ __forceinline__ void gang_barrier(int32_t *ctr, int G, int &round, int &st) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int target = (round + 1) * G;
+    long spins = (st & MD_ST_GANG) ? (1L << 25) : 0;
+    // polled with an atomic (performed where the arrivals are performed)
+    while (__hip_atomic_fetch_add(ctr, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins >= (1L << 25)) {
+        st |= MD_ST_GANG;
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+  ++round;
+}
+
+template <int M>
+__device__ __forceinline__ void newton_path(const md_path &p, int iters, const int32_t *__restrict__ ints,
+                            double *__restrict__ reals, double *__restrict__ wsb,
+                            int32_t *__restrict__ status, int path, double *lds_raw,
+                            int eval_waves, int member, int G, int32_t *gang_ctr) {
+  __shared__ QrShared<M> qsh;
+  __shared__ mdr<M> msh[16];  // one per wave, up to 1024 threads
+  __shared__ int term_next;   // the workgroup's term queue (one workgroup per path)
+  const int N = p.N, n = p.n, d = p.d, L = d + 1;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int wave = tid / WAVE, nwaves = nt / WAVE;
+  const NewtonLayout lay(M, N, n, d, p.M, p.max_deg);
+  char *w = reinterpret_cast<char *>(wsb + p.ws);
+  double *f = reinterpret_cast<double *>(w + lay.off_f);
+  double *A = reinterpret_cast<double *>(w + lay.off_A);
+  double *QR = reinterpret_cast<double *>(w + lay.off_QR);
+  double *vd = reinterpret_cast<double *>(w + lay.off_vd);
+  double *beta = reinterpret_cast<double *>(w + lay.off_beta);
+  double *dx = reinterpret_cast<double *>(w + lay.off_dx);
+  const SolveLayout sl(M, N, n, d);
+  double *r = reinterpret_cast<double *>(w + lay.off_solve + sl.off_r);
+  double *W = reinterpret_cast<double *>(w + lay.off_solve + sl.off_G);
+  double *invd = W + size_t(2) * M * n * N;
+  double *x = reals + p.x;
+  int32_t *gang_terms = reinterpret_cast<int32_t *>(w + lay.off_ctr);
+  EvalArgs a;
+  a.d = d;
+  a.N = N;
+  a.n = n;
+  a.Mt = p.M;
+  a.dc = p.dc;
+  a.Dmax = p.max_deg;
+  a.lay = EvalLayout(M, N, n, d, p.M, p.max_deg);
+  a.S = a.lay.S;
+  a.eq_ptr = ints + p.eq_ptr;
+  a.term_ptr = ints + p.term_ptr;
+  a.factors = ints + p.factors;
+  a.coef = reals + p.coef;
+  a.x = x;
+  a.ws = reinterpret_cast<double *>(w + lay.off_eval);
+  a.Ews = a.lay.E;
+  a.f = f;
+  a.A = A;
+  // stage products: up to eight products per lane, or wider segments (fewer
+  // products per lane, a deeper tree) while all rows still fit in 256 lanes.
+  // The choice depends on the path's sizes only, so the bits do not depend
+  // on the launch shape or the gang split.
+  auto stage_seg = [&](int len, long rows) {
+    int sg = dot_seg_throughput(len);
+    const int smax = len >= WAVE ? WAVE : pow2_at_least(len);
+    while (sg < smax && rows * 2 * sg <= 4 * WAVE) sg *= 2;
+    return sg;
+  };
+  const int seg_dx = stage_seg(N, n);
+  // QR and R^{-1} Q^H: up to four rows per lane, wider segments (fewer rows
+  // per lane) while all columns fit in 512 lanes; sizes only, as above
+  auto col_seg = [&](int cols) {
+    int sg = pow2_at_least((N + 3) / 4);
+    const int smax = N >= WAVE ? WAVE : pow2_at_least(N);
+    while (sg < smax && long(cols) * 2 * sg <= 8 * WAVE) sg *= 2;
+    return sg;
+  };
+  const int seg_q = col_seg(n), seg_p = col_seg(N);
+  const int spw_p = WAVE / seg_p, nslots_p = nwaves * spw_p;
+  const int slot_p = wave * spw_p + lane_id() / seg_p;
+  const int spw_x = WAVE / seg_dx, nslots_x = nwaves * spw_x;
+  const int slot_x = wave * spw_x + lane_id() / seg_dx;
+  const int rgrp = eval_group(d);
+  const int per_wave = term_lds_series(p.max_deg) * L;
+  mdc<M> *lds = reinterpret_cast<mdc<M> *>(lds_raw);
+  const long Ex = long(L) * n, Er = long(L) * N;
+  int st = 0, round = 0;
+  auto gsync = [&] {
+    if (G > 1) gang_barrier(gang_ctr, G, round, st);
+    else __syncthreads();
+  };
+  if (tid == 0) term_next = 0;
+  if (G > 1) {
+    if (member == 0 && tid == 0) *gang_terms = 0;
+    gsync();  // the gang's term queue starts at zero for every member
+  } else {
+    __syncthreads();
+  }
+  for (int it = 0; it < iters; ++it) {
+    // evaluation and differentiation: waves over terms, each wave taking
+    // the next term from a queue (in LDS for a path on one workgroup, in the
+    // path's workspace for a gang), so terms of unequal degree even out;
+    // then the sums, one (equation, coefficient) pair per lane (each wave
+    // clears its rows of A first), with r = -f written by the lane that
+    // formed f
+    if (wave < eval_waves) {
+      auto next_term = [&](int) __attribute__((always_inline)) {
+        int t = 0;
+        if (lane_id() == 0) t = G > 1 ? atomicAdd(gang_terms, 1) : atomicAdd(&term_next, 1);
+        return __shfl(t, 0);
+      };
+      for (int tau = next_term(-1); tau < p.M; tau = next_term(tau))
+        eval_term_wave<M>(a, tau, rgrp, lds + wave * per_wave, [] { wave_sync(); });
+    }
+    gsync();
+    // the queues start again at zero for the next step (read after later
+    // barriers, gang barriers for the gang's queue)
+    if (tid == 0) term_next = 0;
+    if (G > 1 && member == 0 && tid == 0) *gang_terms = 0;
+    for (long g0 = long(member) * nt + wave * WAVE; g0 < long(L) * N; g0 += long(G) * nt)
+      eval_accumulate_wave<M>(a, g0, r, [] { wave_sync(); });
+    gsync();
+    // QR of A_0 (the k = 0 block of A) on member 0, then W = R^{-1}
+    // (Q^H)_{0:n}, columns over all members
+    if (member == 0) {
+      qr_wg<M, 4>(qsh, N, n, seg_q, A, long(L) * N * n, QR, vd, beta, st);
+      inv_diag_range<M>(tid, nt, N, n, QR, invd, st);
+    }
+    gsync();
+    for (int base = member * nslots_p; base < N; base += G * nslots_p) {
+      const int c = base + slot_p;
+      pinv_column<M, 4>(c < N, c, N, n, seg_p, QR, vd, beta, invd, W);
+    }
+    gsync();
+    // staggered substitution: every member forms dx_k, the updates of the
+    // later right hand sides are split over the members
+    for (int k = 0; k <= d; ++k) {
+      for (int base = 0; base < n; base += nslots_x) {
+        const int i = base + slot_x;
+        stage_dx_row<M>(i < n, i, k, N, n, d, seg_dx, W, r, dx, st);
+      }
+      __syncthreads();
+      if (k < d) {
+        const long rows = long(d - k) * N;
+        const int seg_up = stage_seg(n, rows);
+        const int spw_u = WAVE / seg_up, nslots_u = nwaves * spw_u;
+        const int slot_u = wave * spw_u + lane_id() / seg_up;
+        for (long base = long(member) * nslots_u; base < rows; base += long(G) * nslots_u) {
+          const long row = base + slot_u;
+          stage_update_row<M>(row < rows, row, k, N, n, d, seg_up, A, dx, r);
+        }
+        gsync();
+      }
+    }
+    if (member != 0) {
+      if (it + 1 < iters) gsync();
+      continue;
+    }
+    // x += dx and the size of the update (member 0)
+    mdr<M> bd = md_zero<M>(), ba = md_zero<M>();
+    for (long e = tid; e < Ex; e += nt) {
+      const mdc<M> u = cload<M>(dx, Ex, e);
+      cstore<M>(x, Ex, e, c_add<M>(cload<M>(x, Ex, e), u));
+      const mdr<M> a2 = c_abs2<M>(u);
+      if (md_less<M>(ba, a2)) ba = a2;
+      if (e >= long(d) * n && md_less<M>(bd, a2)) bd = a2;
+    }
+    bd = wg_max<M>(bd, msh);
+    ba = wg_max<M>(ba, msh);
+    if (tid == 0 && it == iters - 1) {
+      rstore<M>(reals + p.dx_norm, 2, 0, md_sqrt<M>(bd));
+      rstore<M>(reals + p.dx_norm, 2, 1, md_sqrt<M>(ba));
+    }
+    if (it + 1 < iters) gsync();
+    else __syncthreads();
+  }
+  if (tid == 0) {
+    if (st) atomicOr(status + path, st);
+    if (member == 0) atomicAnd(status + path, ~MD_ST_NOTRUN);
+  }
+}
+
+// BLOCK threads per workgroup; HI: the kernel of penta, octo and deca double
+// paths (m in {5, 8, 10}), else of double to quad double (m in 1..4).
+template <int BLOCK, bool HI>
+__global__ void __launch_bounds__(BLOCK) k_newton_batch(int npaths, const md_path *__restrict__ paths,
+                                                        const int32_t *__restrict__ jobs, int nq,
+                                                        const int32_t *__restrict__ qbegin,
+                                                        const int32_t *__restrict__ ints,
+                                                        double *__restrict__ reals,
+                                                        double *__restrict__ wsb, int iters,
+                                                        int32_t *counters, int32_t *gang_ctr,
+                                                        int32_t *status, int eval_waves,
+                                                        int64_t *clk) {
+  extern __shared__ double lds_raw[];
+  __shared__ int sh_job;
+  const int q = nq == 1 ? 0 : xcc_id() % nq;
+  const int begin = qbegin[q], end = qbegin[q + 1];
+  // Every single-thread action of the job loop (taking the next job, the
+  // status of a refused path, the path's end clock) sits in one leader block
+  // between two barriers, and the loop has no other exit or back edge.  A
+  // leader-only block at the loop head with a `continue` elsewhere lets the
+  // compiler route the other lanes' back edge around it straight to the
+  // barrier; the loop then becomes divergent and those lanes spin on a stale
+  // job while the leader waits, masked off, for them to leave.
+  if (threadIdx.x == 0) sh_job = begin + atomicAdd(counters + q, 1);
+  __syncthreads();
+  int job = __builtin_amdgcn_readfirstlane(sh_job);
+  while (job < end) {
+    const int path = jobs[2 * job];
+    const int G = jobs[2 * job + 1] >> 8, member = jobs[2 * job + 1] & 0xff;
+    const bool known = path >= 0 && path < npaths;
+    bool ok = false;
+    md_path p{};
+    if (known) {
+      p = paths[path];
+      ok = G >= 1 && member < G && p.N >= p.n && p.n >= 1 && p.N <= WAVE && p.d >= 0 &&
+           p.max_deg >= 0 &&
+           (HI ? (p.m == 5 || p.m == 8 || p.m == 10) : (p.m >= 1 && p.m <= 4));
+    }
+    if (ok) {
+      if (clk && threadIdx.x == 0 && member == 0) clk[2 * path] = wall_clock64();
+      int32_t *gc = gang_ctr + path;
+      if constexpr (HI) {
+        switch (p.m) {
+          case 5: newton_path<5>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc); break;
+          case 8: newton_path<8>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc); break;
+          default: newton_path<10>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc); break;
+        }
+      } else {
+        switch (p.m) {
+          case 1: newton_path<1>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc); break;
+          case 2: newton_path<2>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc); break;
+          case 3: newton_path<3>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc); break;
+          default: newton_path<4>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc); break;
+        }
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (known && !ok) atomicOr(status + path, MD_ST_BADPATH);
+      if (ok && clk && member == 0) clk[2 * path + 1] = wall_clock64();
+      sh_job = begin + atomicAdd(counters + q, 1);
+    }
+    __syncthreads();
+    job = __builtin_amdgcn_readfirstlane(sh_job);
+  }
+}
+
+// Launches of the two instantiations (batch.hip: m in 1..4, 256 or 512
+// threads; batch_hi.hip: m in {5, 8, 10}, 256 threads).
+void launch_newton_batch_lo(int block, int grid, size_t lds, hipStream_t s, int npaths,
+                            const md_path *paths, const int32_t *jobs, int nq,
+                            const int32_t *qbegin, const int32_t *ints, double *reals, double *ws,
+                            int iters, int32_t *counters, int32_t *gang_ctr, int32_t *status,
+                            int eval_waves, int64_t *clk);
+void launch_newton_batch_hi(int grid, size_t lds, hipStream_t s, int npaths, const md_path *paths,
+                            const int32_t *jobs, int nq, const int32_t *qbegin,
+                            const int32_t *ints, double *reals, double *ws, int iters,
+                            int32_t *counters, int32_t *gang_ctr, int32_t *status, int eval_waves,
+                            int64_t *clk);
+
+}  // namespace mds

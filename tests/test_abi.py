@@ -124,9 +124,12 @@ def test_batch_host_checks(lib):
         return lib.md_newton_batch(npaths, paths, njobs, fake, nq, fake, fake, fake, fake, iters,
                                    fake, fake, fake, max_m, max_N, max_d, max_deg, grid, block, ew,
                                    None, None)
-    # penta double paths are not carried by the batched kernel: rejected on the host
-    assert call(max_m=5) == 1
+    # limb counts outside both batched kernels are rejected on the host, and
+    # the penta to deca double kernel runs 256-thread workgroups only
+    assert call(max_m=6) == 1
+    assert call(max_m=9) == 1
     assert call(max_m=0) == 1
+    assert call(max_m=8, block=512, ew=4) == 1
     # neither are paths of more than 64 equations
     assert call(max_N=65) == 2
     assert b"max_N=65" in lib.md_last_error()
@@ -143,7 +146,8 @@ def test_batch_host_checks(lib):
     # evaluation LDS above the device limit is refused (deca-size series on 4 waves)
     assert lib.md_batch_lds_bytes(4, 200, 4, 4) > 64 * 1024
     assert call(max_d=200, max_deg=4) == 2
-    assert lib.md_batch_lds_bytes(5, 8, 3, 4) == 0
+    assert lib.md_batch_lds_bytes(6, 8, 3, 4) == 0
+    assert lib.md_batch_lds_bytes(10, 8, 3, 4) == 10 * lib.md_batch_lds_bytes(1, 8, 3, 4)
     lib.md_device_dies.argtypes = [P, i, P]
     assert lib.md_device_dies(None, 4, None) == 3
     assert lib.md_device_dies(fake, 0, None) == 1

@@ -536,3 +536,56 @@ def test_batch_flags_refused_paths(B):
         assert np.array_equal(host(batch.x(p)), host(ref.x(p))), p
     for p in (1, 3):
         assert np.array_equal(host(batch.x(p)), paths[p][1]), p     # untouched
+
+
+def hp_batch(count=6, seed=0):
+    specs = I.batch_specs((996, seed), count, n_choices=(3, 5, 8, 12), d_range=(0, 9),
+                          m_choices=(5, 8, 10))
+    paths = []
+    for s in specs:
+        sysm, x0 = I.newton_system((997, s.path), s.n, s.m, terms=4, max_deg=3)
+        paths.append((sysm, I.series_start(x0, s.d)))
+    return paths
+
+
+def test_batch_high_precision_against_oracle_and_per_path(B):
+    """Penta, octo and deca double paths in one launch of the 256-thread
+    kernel: against the oracle and md_newton_step after 2 steps (agreement
+    rule), and the same bits under another launch shape, job order and a
+    gang split."""
+    paths = hp_batch()
+    batch = B.BatchedPaths(paths)
+    print("high-precision batch:", [(s.m, s.n, x.shape[2] - 1) for s, x in paths], flush=True)
+    B.md_newton_batch(batch, 2)
+    st = host(batch.status)
+    assert not st.any(), st
+    first = [host(batch.x(p)).copy() for p in range(len(paths))]
+    batch.restore()
+    gangs = np.ones(len(paths), dtype=np.int64)
+    gangs[int(np.argmax(batch.cost))] = 3
+    batch.set_schedule(gangs=gangs)
+    B.md_newton_batch(batch, 2, grid=7, eval_waves=2)
+    assert not host(batch.status).any()
+    for p, (sysm, x) in enumerate(paths):
+        assert np.array_equal(host(batch.x(p)), first[p]), p
+        m = sysm.m
+        xw, _, _ = oracle.newton(sysm, x, 2)
+        xg = dev(x)
+        sd = B.DeviceSystem(sysm)
+        for _ in range(2):
+            B.md_newton_step(sd, xg)
+        cond = sysm.meta["cond_A0_double"]
+        for ref in (xw, host(xg)):
+            e = rel_err_per_k(first[p], ref)
+            for k in range(x.shape[2]):
+                assert e[k] <= tol(m, math.log2(cond) + math.log2(k + 1) + 4), (p, k, e)
+
+
+def test_batch_high_precision_refuses_mixed_and_512(B):
+    paths = hp_batch(count=2, seed=1)
+    lo = small_batch(count=2, seed=4)
+    with pytest.raises(B.MdError, match="separate launches"):
+        B.BatchedPaths(paths + lo)
+    batch = B.BatchedPaths(paths)
+    with pytest.raises(B.MdError, match="block=256"):
+        B.md_newton_batch(batch, 1, block=512, eval_waves=4)

@@ -106,8 +106,9 @@ def test_cpu_baseline_pool():
 
 def test_batch_refuses_paths_the_kernel_does_not_carry():
     """BatchedPaths refuses, on the host, a path above 64 equations, with
-    N < n, or in a precision above quad double, so that md_newton_batch is
-    never given one (its kernel would only flag it MD_ST_BADPATH)."""
+    N < n, with a limb count no batched kernel carries, or of both classes
+    of precision at once, so that md_newton_batch is never given one (its
+    kernel would only flag it MD_ST_BADPATH)."""
     paths = tiny_paths(3)
     m, n = 2, 70
     one = ([1.0] + [0.0] * (m - 1), [0.0] * m)
@@ -120,10 +121,20 @@ def test_batch_refuses_paths_the_kernel_does_not_carry():
                                         [((1, 2), [one]), ((), [mone])]])
     with pytest.raises(B.MdError, match="n <= N"):
         B.BatchedPaths([(under, np.zeros((2, m, 3, 3)))], device="cpu")
-    # penta double
+    # penta double next to double-double paths: the two classes of
+    # precision run in separate launches
     sys5, x5 = I.newton_system((995, 0), 3, 5, terms=3, max_deg=2)
-    with pytest.raises(B.MdError, match="m=5"):
+    with pytest.raises(B.MdError, match="separate launches"):
         B.BatchedPaths(paths + [(sys5, I.series_start(x5, 2))], device="cpu")
+    # penta and octo double together are one class
+    sys8, x8 = I.newton_system((995, 1), 3, 8, terms=3, max_deg=2)
+    hb = B.BatchedPaths([(sys5, I.series_start(x5, 2)), (sys8, I.series_start(x8, 3))],
+                        device="cpu")
+    assert hb.max_m == 8
+    # a limb count no kernel carries
+    sys6, x6 = I.newton_system((995, 2), 3, 6, terms=3, max_deg=2)
+    with pytest.raises(B.MdError, match="m=6"):
+        B.BatchedPaths([(sys6, I.series_start(x6, 2))], device="cpu")
     # the largest accepted shapes pass, and the batch records its maxima
     batch = B.BatchedPaths(paths, device="cpu")
     assert batch.max_N == max(s.N for s, _ in paths) and batch.max_m <= 4
