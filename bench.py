@@ -366,6 +366,7 @@ def high_precision(args, B, OC) -> dict:
         conv_ops = OC.convolve(32, 64).table_ops(m)
         nrm = B.md_norm2(torch.as_tensor(I.unit_complex(I.rng(951, m), m, 64), device="cuda"))
         torch.cuda.synchronize()
+        gang = gang_step(B, OC, m, args.hp_reps)
         out[name] = {
             "ms_per_step": round(ms, 3),
             "kernels_ms": {k: round(v, 3) for k, v in dur.items()},
@@ -377,9 +378,45 @@ def high_precision(args, B, OC) -> dict:
             "convolve_pct_fp64_vector_peak": round(100.0 * conv_ops / (conv_ms * 1e-3)
                                                    / OC.FP64_VECTOR_PEAK, 3),
             "norm2_of_64_unit_numbers_limb0": float(nrm[0, 0].item()),
+            "gang_newton_step": gang,
             "status": r["status"],
         }
     return out
+
+
+HP_GANG = 32
+
+
+def gang_step(B, OC, m: int, reps: int) -> dict:
+    """One whole Newton step (eval/diff, QR, R^{-1} Q^H, staggered solve,
+    update) of the same 64 x 64 system at the same unit series point (d =
+    32), as one path on a gang of HP_GANG workgroups of the persistent
+    kernel (the members split terms, Jacobian rows, QR columns, columns of
+    R^{-1} Q^H and right-hand-side updates); mean of `reps` launches."""
+    import numpy as np
+    import torch
+    from paper_2012_06607_amd import inputs as I
+    sysm = I.eval_system((3, 0), 64, 64, m, 16, 4)
+    x = I.unit_series((3, 1), m, 32, 64)
+    batch = B.BatchedPaths([(sysm, x)])
+    batch.set_schedule(gangs=np.array([HP_GANG]))
+    stream = torch.cuda.current_stream()
+    times = []
+    for rep in range(reps + 1):
+        batch.restore()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        B.md_newton_batch(batch, 1, grid=HP_GANG, block=256, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if rep:
+            times.append(e0.elapsed_time(e1))
+    ms = float(np.mean(times))
+    ops = OC.newton_step(sysm, 32, m).table_ops(m)
+    return {"gang": HP_GANG, "ms_per_step": round(ms, 3),
+            "pct_fp64_vector_peak": round(100.0 * ops / (ms * 1e-3) / OC.FP64_VECTOR_PEAK, 4),
+            "status": int(batch.status.max().item())}
 
 
 def adjoint_measure(args, B, OC) -> dict:
@@ -398,7 +435,13 @@ def adjoint_measure(args, B, OC) -> dict:
     stream = torch.cuda.current_stream()
     ws_n = B.workspace(B.MD_FN_NEWTON, m, n, n, d, sysm.M, sysm.max_deg)
     st = torch.zeros(1, dtype=torch.int32, device="cuda")
-    nrm = torch.empty((m, 2), dtype=torch.float64, device="cuda")
+    # zero: each step's update is not compared with an earlier one (the
+    # growth bit MD_ST_DIVERGED is expected while the series converges)
+    nrm = torch.zeros((m, 2), dtype=torch.float64, device="cuda")
+
+    def step():
+        nrm.zero_()
+        B.md_newton_step(sd, x, nrm, ws_n, st, stream)
 
     def timed(fn, reps):
         out = []
@@ -411,8 +454,7 @@ def adjoint_measure(args, B, OC) -> dict:
             out.append(e0.elapsed_time(e1))
         return float(np.median(out))
 
-    ms_fwd = timed(lambda: [B.md_newton_step(sd, x, nrm, ws_n, st, stream)
-                            for _ in range(iters)], 1) / iters
+    ms_fwd = timed(lambda: [step() for _ in range(iters)], 1) / iters
     G = 2 * x
     res, grads = {}, {}
     for store in (True, False):

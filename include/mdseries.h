@@ -304,10 +304,10 @@ int md_norm2(int m, int64_t count, const double *x, double *out, void *stream);
  * and gang split gives the same bits.
  *
  * One path, in a device array of md_path (all offsets are element offsets):
- *   m in 1..4 (double to quad double) or in {5, 8, 10} (penta, octo and
- *   deca double, a kernel of its own with 256-thread workgroups): a launch
- *   takes the kernel of its max_m, and a path of the other class in it gets
- *   MD_ST_BADPATH; 1 <= n <= N <= 64, d >= 0 (md_newton_batch refuses a
+ *   m in 1..4 (double to quad double, one kernel), or one of 5, 8, 10
+ *   (penta, octo, deca double: a kernel each, 256-thread workgroups): a
+ *   launch takes the kernel of its max_m, and a path that kernel does not
+ *   carry gets MD_ST_BADPATH; 1 <= n <= N <= 64, d >= 0 (md_newton_batch refuses a
  *   batch whose max_m or max_N is outside these ranges; a path table that
  *   breaks them anyway gets MD_ST_BADPATH for that path, which is then not
  *   run);

@@ -471,9 +471,11 @@ class BatchedPaths:
             # R^{-1} Q^H segments)
             if m not in BATCH_LO_M + BATCH_HI_M:
                 raise MdError(f"path {p}: m={m} is not carried by the batched kernels")
-            if (m in BATCH_HI_M) != (sysm_class(paths[0][0].m)):
-                raise MdError(f"path {p}: m={m} and m={paths[0][0].m} in one batch (double to "
-                              "quad double and penta to deca double run in separate launches)")
+            m0 = paths[0][0].m
+            if (m in BATCH_HI_M) != sysm_class(m0) or (m in BATCH_HI_M and m != m0):
+                raise MdError(f"path {p}: m={m} and m={m0} in one batch (double to quad double "
+                              "run in one launch, and penta, octo and deca double each in "
+                              "separate launches)")
             if not 1 <= sysm.n <= sysm.N <= BATCH_MAX_N:
                 raise MdError(f"path {p}: needs 1 <= n <= N <= {BATCH_MAX_N} "
                               f"(n={sysm.n}, N={sysm.N})")

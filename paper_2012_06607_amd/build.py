@@ -72,12 +72,26 @@ def _compile(src: str) -> str:
     return obj
 
 
-def _stale(src: str, headers_mtime: float) -> bool:
+def _includes(path: str, seen: set[str]) -> set[str]:
+    """Files reached from `path` through #include "..." (quoted includes
+    resolved next to the including file or in include/)."""
+    for name in re.findall(r'^\s*#include\s+"([^"]+)"', open(path).read(), re.M):
+        for base in (os.path.dirname(path), os.path.join(ROOT, "include")):
+            cand = os.path.normpath(os.path.join(base, name))
+            if os.path.exists(cand):
+                if cand not in seen:
+                    seen.add(cand)
+                    _includes(cand, seen)
+                break
+    return seen
+
+
+def _stale(src: str) -> bool:
     obj = os.path.join(OBJ, os.path.basename(src)[:-4] + ".o")
     if not os.path.exists(obj):
         return True
     t = os.path.getmtime(obj)
-    return t < os.path.getmtime(src) or t < headers_mtime
+    return any(t < os.path.getmtime(f) for f in {src} | _includes(src, set()))
 
 
 def build(jobs: int | None = None, verbose: bool = False, changed_only: bool = False) -> str:
@@ -88,9 +102,7 @@ def build(jobs: int | None = None, verbose: bool = False, changed_only: bool = F
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     todo = srcs
     if changed_only:
-        hdrs = glob.glob(os.path.join(CSRC, "*.hpp")) + glob.glob(os.path.join(ROOT, "include", "*.h"))
-        hm = max((os.path.getmtime(h) for h in hdrs), default=0.0)
-        todo = [s for s in srcs if _stale(s, hm)]
+        todo = [s for s in srcs if _stale(s)]
     jobs = jobs or min(max(len(todo), 1), max(1, min(16, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         list(ex.map(_compile, todo))

@@ -13,10 +13,11 @@
 //
 // A large path may be a gang of G workgroups (G members, one job each).
 // The members split the term evaluations, the Jacobian rows, the columns of
-// R^{-1} Q^H and the right-hand-side updates, and meet at gang barriers (a
-// counter in device memory, with device-scope release and acquire).  The QR
-// and the update of x run on member 0; every member computes the stage
-// products dx_k itself (the same bits), so a stage costs one gang barrier.
+// each QR step, the columns of R^{-1} Q^H and the right-hand-side updates,
+// and meet at gang barriers (a counter in device memory, with device-scope
+// release and acquire).  The update of x runs on member 0; every member
+// computes the stage products dx_k itself (the same bits), so a stage costs
+// one gang barrier.
 // With one queue per accelerator die (queue q served by the workgroups on
 // die q) a gang's members share that die's L2.
 #include "batch_kernel.hpp"
@@ -41,11 +42,11 @@ void launch_newton_batch_lo(int block, int grid, size_t lds, hipStream_t s, int 
                             int iters, int32_t *counters, int32_t *gang_ctr, int32_t *status,
                             int eval_waves, int64_t *clk) {
   if (block == 256)
-    k_newton_batch<256, false><<<dim3(grid), dim3(256), lds, s>>>(
+    k_newton_batch<256, 0><<<dim3(grid), dim3(256), lds, s>>>(
         npaths, paths, jobs, nq, qbegin, ints, reals, ws, iters, counters, gang_ctr, status,
         eval_waves, clk);
   else
-    k_newton_batch<512, false><<<dim3(grid), dim3(512), lds, s>>>(
+    k_newton_batch<512, 0><<<dim3(grid), dim3(512), lds, s>>>(
         npaths, paths, jobs, nq, qbegin, ints, reals, ws, iters, counters, gang_ctr, status,
         eval_waves, clk);
 }
@@ -96,9 +97,15 @@ extern "C" int md_newton_batch(int npaths, const md_path *paths, int njobs, cons
   if (max_m <= 4)
     launch_newton_batch_lo(block, grid, lds, s, npaths, paths, jobs, nq, qbegin, ints, reals, ws,
                            iters, counters, gang_ctr, status, eval_waves, path_clock);
+  else if (max_m == 5)
+    launch_newton_batch_m5(grid, lds, s, npaths, paths, jobs, nq, qbegin, ints, reals, ws,
+                              iters, counters, gang_ctr, status, eval_waves, path_clock);
+  else if (max_m == 8)
+    launch_newton_batch_m8(grid, lds, s, npaths, paths, jobs, nq, qbegin, ints, reals, ws,
+                              iters, counters, gang_ctr, status, eval_waves, path_clock);
   else
-    launch_newton_batch_hi(grid, lds, s, npaths, paths, jobs, nq, qbegin, ints, reals, ws, iters,
-                           counters, gang_ctr, status, eval_waves, path_clock);
+    launch_newton_batch_m10(grid, lds, s, npaths, paths, jobs, nq, qbegin, ints, reals, ws,
+                               iters, counters, gang_ctr, status, eval_waves, path_clock);
   return check_launch("md_newton_batch");
 }
 

@@ -13,10 +13,11 @@
 //
 // A large path may be a gang of G workgroups (G members, one job each).
 // The members split the term evaluations, the Jacobian rows, the columns of
-// R^{-1} Q^H and the right-hand-side updates, and meet at gang barriers (a
-// counter in device memory, with device-scope release and acquire).  The QR
-// and the update of x run on member 0; every member computes the stage
-// products dx_k itself (the same bits), so a stage costs one gang barrier.
+// each QR step, the columns of R^{-1} Q^H and the right-hand-side updates,
+// and meet at gang barriers (a counter in device memory, with device-scope
+// release and acquire).  The update of x runs on member 0; every member
+// computes the stage products dx_k itself (the same bits), so a stage costs
+// one gang barrier.
 // With one queue per accelerator die (queue q served by the workgroups on
 // die q) a gang's members share that die's L2.
 #pragma once
@@ -83,6 +84,80 @@ __device__ __forceinline__ void gang_barrier(int32_t *ctr, int G, int &round, in
   }
   __syncthreads();
   ++round;
+}
+
+// Householder QR of A_0 by all G workgroups of a gang: the columns of each
+// step go over the slots of every member, the first wave of member 0
+// updates column j+1 and forms reflector j+1 from it (as qr_wg's look-ahead
+// does), and a gang barrier ends each step.  The reflector scalars are read
+// back from vdiag and beta (written by member 0 before the barrier).  Each
+// column is updated by one segment with the same code as in qr_wg, so the
+// factors are those of qr_wg bit for bit.
+template <int M, int RPL, class Sync>
+__device__ __forceinline__ void qr_gang(QrShared<M> &sh, int N, int n, int seg,
+                                        const double *__restrict__ A0, long A0E,
+                                        double *__restrict__ QR, double *__restrict__ vdiag,
+                                        double *__restrict__ beta, int &st, int member, int G,
+                                        Sync gsync) {
+  const long E = long(N) * n;
+  const int lane = lane_id();
+  const int wave = threadIdx.x / WAVE;
+  const int nwaves = blockDim.x / WAVE;
+  const int lis = lane & (seg - 1);
+  const int spw = WAVE / seg;
+  const int nslots = nwaves * spw;
+  const int gs = member * nslots + wave * spw + lane / seg;  // global slot
+  const int GS = G * nslots, others = GS - spw;
+  const bool lead = member == 0 && wave == 0;
+  for (long e = long(member) * blockDim.x + threadIdx.x; e < E; e += long(G) * blockDim.x)
+    cstore<M>(QR, E, e, cload<M>(A0, A0E, e));
+  gsync();
+  for (int j = -1; j < n; ++j) {
+    constexpr bool HOLD = RPL < 4;
+    mdc<M> vi[RPL], anew[RPL];
+    mdc<M> v0 = c_zero<M>();
+    mdr<M> bet = md_zero<M>();
+    if (j >= 0) {
+      v0 = cload<M>(vdiag, n, j);
+      bet = rload<M>(beta, n, j);
+      if constexpr (HOLD) {
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+          const int i = lis + r * seg;
+          vi[r] = c_zero<M>();
+          if (i == j) vi[r] = v0;
+          else if (i > j && i < N) vi[r] = cload<M>(QR, E, long(i) * n + j);
+        }
+      }
+    }
+    // round 0: global slot gs takes column j+1+gs; later rounds: the slots
+    // outside the lead wave take the columns that are left
+    const int ncols = n - j - 1;
+    int rounds = 0;
+    if (j < 0) {
+      rounds = lead ? 1 : 0;
+    } else if (ncols > 0) {
+      const int rest = ncols - GS;
+      rounds = lead ? 1 : 1 + (rest > 0 ? (rest + others - 1) / others : 0);
+    }
+    for (int k = 0; k < rounds; ++k) {
+      const int l = k == 0 ? j + 1 + gs : j + 1 + GS + (k - 1) * others + (gs - spw);
+      if (j < 0) {
+        if constexpr (HOLD) {
+#pragma unroll
+          for (int r = 0; r < RPL; ++r) {
+            const int i = lis + r * seg;
+            anew[r] = (l < n && i < N) ? cload<M>(QR, E, long(i) * n + l) : c_zero<M>();
+          }
+        }
+      } else {
+        qr_update_column<M, RPL, HOLD>(l < n, l, j, N, n, seg, vi, v0, bet, QR, E, anew);
+      }
+      if (k == 0 && lead && j + 1 < n)
+        qr_reflector<M, RPL, HOLD>(anew, j + 1, N, n, seg, true, sh, QR, E, vdiag, beta, st);
+    }
+    gsync();
+  }
 }
 
 template <int M>
@@ -192,9 +267,12 @@ __device__ __forceinline__ void newton_path(const md_path &p, int iters, const i
     for (long g0 = long(member) * nt + wave * WAVE; g0 < long(L) * N; g0 += long(G) * nt)
       eval_accumulate_wave<M>(a, g0, r, [] { wave_sync(); });
     gsync();
-    // QR of A_0 (the k = 0 block of A) on member 0, then W = R^{-1}
-    // (Q^H)_{0:n}, columns over all members
-    if (member == 0) {
+    // QR of A_0 (the k = 0 block of A), its columns over all members of a
+    // gang, then W = R^{-1} (Q^H)_{0:n}, columns over all members
+    if (G > 1) {
+      qr_gang<M, 4>(qsh, N, n, seg_q, A, long(L) * N * n, QR, vd, beta, st, member, G, gsync);
+      if (member == 0) inv_diag_range<M>(tid, nt, N, n, QR, invd, st);
+    } else {
       qr_wg<M, 4>(qsh, N, n, seg_q, A, long(L) * N * n, QR, vd, beta, st);
       inv_diag_range<M>(tid, nt, N, n, QR, invd, st);
     }
@@ -252,9 +330,10 @@ __device__ __forceinline__ void newton_path(const md_path &p, int iters, const i
   }
 }
 
-// BLOCK threads per workgroup; HI: the kernel of penta, octo and deca double
-// paths (m in {5, 8, 10}), else of double to quad double (m in 1..4).
-template <int BLOCK, bool HI>
+// BLOCK threads per workgroup; MS: 0 for the kernel of double to quad
+// double paths (m in 1..4), else the one limb count (5, 8 or 10) the
+// kernel carries (one translation unit each: these compile slowly).
+template <int BLOCK, int MS>
 __global__ void __launch_bounds__(BLOCK) k_newton_batch(int npaths, const md_path *__restrict__ paths,
                                                         const int32_t *__restrict__ jobs, int nq,
                                                         const int32_t *__restrict__ qbegin,
@@ -288,17 +367,13 @@ __global__ void __launch_bounds__(BLOCK) k_newton_batch(int npaths, const md_pat
       p = paths[path];
       ok = G >= 1 && member < G && p.N >= p.n && p.n >= 1 && p.N <= WAVE && p.d >= 0 &&
            p.max_deg >= 0 &&
-           (HI ? (p.m == 5 || p.m == 8 || p.m == 10) : (p.m >= 1 && p.m <= 4));
+           (MS ? p.m == MS : (p.m >= 1 && p.m <= 4));
     }
     if (ok) {
       if (clk && threadIdx.x == 0 && member == 0) clk[2 * path] = wall_clock64();
       int32_t *gc = gang_ctr + path;
-      if constexpr (HI) {
-        switch (p.m) {
-          case 5: newton_path<5>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc); break;
-          case 8: newton_path<8>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc); break;
-          default: newton_path<10>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc); break;
-        }
+      if constexpr (MS != 0) {
+        newton_path<MS>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc);
       } else {
         switch (p.m) {
           case 1: newton_path<1>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc); break;
@@ -319,17 +394,21 @@ __global__ void __launch_bounds__(BLOCK) k_newton_batch(int npaths, const md_pat
   }
 }
 
-// Launches of the two instantiations (batch.hip: m in 1..4, 256 or 512
-// threads; batch_hi.hip: m in {5, 8, 10}, 256 threads).
+// Launches of the instantiations (batch.hip: m in 1..4, 256 or 512
+// threads; batch_m5.hip, batch_m8.hip, batch_m10.hip: one limb count each,
+// 256 threads).
 void launch_newton_batch_lo(int block, int grid, size_t lds, hipStream_t s, int npaths,
                             const md_path *paths, const int32_t *jobs, int nq,
                             const int32_t *qbegin, const int32_t *ints, double *reals, double *ws,
                             int iters, int32_t *counters, int32_t *gang_ctr, int32_t *status,
                             int eval_waves, int64_t *clk);
-void launch_newton_batch_hi(int grid, size_t lds, hipStream_t s, int npaths, const md_path *paths,
-                            const int32_t *jobs, int nq, const int32_t *qbegin,
-                            const int32_t *ints, double *reals, double *ws, int iters,
-                            int32_t *counters, int32_t *gang_ctr, int32_t *status, int eval_waves,
-                            int64_t *clk);
+#define MDS_BATCH_WIDE_LAUNCH(NAME)                                                              \
+  void NAME(int grid, size_t lds, hipStream_t s, int npaths, const md_path *paths,              \
+            const int32_t *jobs, int nq, const int32_t *qbegin, const int32_t *ints,            \
+            double *reals, double *ws, int iters, int32_t *counters, int32_t *gang_ctr,         \
+            int32_t *status, int eval_waves, int64_t *clk)
+MDS_BATCH_WIDE_LAUNCH(launch_newton_batch_m5);
+MDS_BATCH_WIDE_LAUNCH(launch_newton_batch_m8);
+MDS_BATCH_WIDE_LAUNCH(launch_newton_batch_m10);
 
 }  // namespace mds

@@ -538,9 +538,9 @@ def test_batch_flags_refused_paths(B):
         assert np.array_equal(host(batch.x(p)), paths[p][1]), p     # untouched
 
 
-def hp_batch(count=6, seed=0):
+def hp_batch(count=6, seed=0, m=8):
     specs = I.batch_specs((996, seed), count, n_choices=(3, 5, 8, 12), d_range=(0, 9),
-                          m_choices=(5, 8, 10))
+                          m_choices=(m,))
     paths = []
     for s in specs:
         sysm, x0 = I.newton_system((997, s.path), s.n, s.m, terms=4, max_deg=3)
@@ -548,12 +548,13 @@ def hp_batch(count=6, seed=0):
     return paths
 
 
-def test_batch_high_precision_against_oracle_and_per_path(B):
-    """Penta, octo and deca double paths in one launch of the 256-thread
+@pytest.mark.parametrize("m", (5, 8, 10))
+def test_batch_high_precision_against_oracle_and_per_path(B, m):
+    """Penta, octo or deca double paths in one launch of their 256-thread
     kernel: against the oracle and md_newton_step after 2 steps (agreement
     rule), and the same bits under another launch shape, job order and a
     gang split."""
-    paths = hp_batch()
+    paths = hp_batch(m=m)
     batch = B.BatchedPaths(paths)
     print("high-precision batch:", [(s.m, s.n, x.shape[2] - 1) for s, x in paths], flush=True)
     B.md_newton_batch(batch, 2)

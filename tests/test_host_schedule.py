@@ -126,9 +126,13 @@ def test_batch_refuses_paths_the_kernel_does_not_carry():
     sys5, x5 = I.newton_system((995, 0), 3, 5, terms=3, max_deg=2)
     with pytest.raises(B.MdError, match="separate launches"):
         B.BatchedPaths(paths + [(sys5, I.series_start(x5, 2))], device="cpu")
-    # penta and octo double together are one class
+    # penta and octo double have a kernel each: not in one batch; two octo
+    # double paths are
     sys8, x8 = I.newton_system((995, 1), 3, 8, terms=3, max_deg=2)
-    hb = B.BatchedPaths([(sys5, I.series_start(x5, 2)), (sys8, I.series_start(x8, 3))],
+    with pytest.raises(B.MdError, match="separate launches"):
+        B.BatchedPaths([(sys5, I.series_start(x5, 2)), (sys8, I.series_start(x8, 3))],
+                       device="cpu")
+    hb = B.BatchedPaths([(sys8, I.series_start(x8, 2)), (sys8, I.series_start(x8, 3))],
                         device="cpu")
     assert hb.max_m == 8
     # a limb count no kernel carries
