@@ -219,7 +219,8 @@ def batched(args, B, OC, paths):
         torch.cuda.synchronize()
         times.append(e0.elapsed_time(e1))
     ms = float(np.mean(times))
-    res = {"ms": ms, "ops": ops, "shape": shape, "times": times,
+    phases = phase_breakdown(B, batch, ITERS, shape, stream)
+    res = {"ms": ms, "ops": ops, "shape": shape, "times": times, "phases": phases,
            "status": int(batch.status.max().item()), "tuned": tuned, "batch": batch,
            "qd_share": sum(ITERS * OC.newton_step(s, x.shape[2] - 1, s.m).table_ops(s.m)
                            for s, x in paths if s.m == 4) / ops}
@@ -256,6 +257,29 @@ def batched(args, B, OC, paths):
             worst = max(worst, float((diff / size).max()) / 2.0 ** -(53 * sysm.m - 8))
         res["diff_units"] = worst
     return res
+
+
+PHASES = ("evaluation", "sums into f and A", "QR", "R^-1 Q^H", "stages", "update")
+
+
+def phase_breakdown(B, batch, iters, shape, stream) -> dict:
+    """One more launch (outside any timed region) with the kernel's phase
+    clocks on: the device wall-clock seconds each phase took, summed over
+    the paths (member 0 of each path measures; a phase ends at a barrier),
+    split by precision."""
+    import numpy as np
+    import torch
+    clk = torch.zeros((batch.npaths, 8), dtype=torch.int64, device="cuda")
+    batch.restore()
+    B.md_newton_batch(batch, iters, stream=stream, phase_clock=clk, **shape)
+    torch.cuda.synchronize()
+    hz = B.md_wall_clock_hz()
+    c = clk.cpu().numpy()[:, :len(PHASES)] / hz
+    ms_ = np.array([m for (m, _, _, _) in batch.meta])
+    out = {"total_s": {ph: round(float(c[:, i].sum()), 4) for i, ph in enumerate(PHASES)}}
+    for m in sorted(set(ms_.tolist())):
+        out[f"m{m}_s"] = {ph: round(float(c[ms_ == m, i].sum()), 4) for i, ph in enumerate(PHASES)}
+    return out
 
 
 def solve_eval(B, OC, m: int, n: int, d: int, key: int, reps: int, warm: int) -> dict:
@@ -414,7 +438,9 @@ def gang_step(B, OC, m: int, reps: int) -> dict:
             times.append(e0.elapsed_time(e1))
     ms = float(np.mean(times))
     ops = OC.newton_step(sysm, 32, m).table_ops(m)
+    ph = phase_breakdown(B, batch, 1, {"grid": HP_GANG, "block": 256}, stream)["total_s"]
     return {"gang": HP_GANG, "ms_per_step": round(ms, 3),
+            "phases_ms": {k: round(v * 1e3, 3) for k, v in ph.items()},
             "pct_fp64_vector_peak": round(100.0 * ops / (ms * 1e-3) / OC.FP64_VECTOR_PEAK, 4),
             "status": int(batch.status.max().item())}
 
@@ -613,6 +639,7 @@ def main():
                               "events on the launch stream); traffic: HBM bytes per launch "
                               "from FETCH_SIZE + WRITE_SIZE, copy-scaled"},
         "qd_share_of_ops": round(r["qd_share"], 4),
+        "phases_s": r["phases"],
         "status": r["status"],
     }
     if r.get("tuned"):

@@ -354,7 +354,11 @@ size_t md_batch_lds_bytes(int max_m, int max_d, int max_deg, int eval_waves);
  * waves per workgroup that
  * evaluate terms; path_clock (may be NULL): device int64[2*npaths],
  * receives for every path the device wall clock (md_wall_clock_hz ticks per
- * second) when its member 0 took it and when it finished.
+ * second) when its member 0 took it and when it finished; phase_clock (may
+ * be NULL): device int64[8*npaths], zeroed by the caller, to which member 0
+ * adds the wall-clock ticks of each phase of every step: [0] evaluation of
+ * the terms, [1] sums into f and A, [2] QR of A_0, [3] R^{-1} Q^H, [4] the
+ * staggered stages, [5] the update of x (slots 6, 7 unused).
  * Errors: MD_EINVAL (max_m not in 1..4, 5, 8, 10; block 512 with max_m >= 5;
  * among others), MD_ENULL, MD_ESHAPE
  * (max_N outside 1..64, or LDS above md_device_lds_bytes()), MD_EHIP. */
@@ -362,7 +366,37 @@ int md_newton_batch(int npaths, const md_path *paths, int njobs, const int32_t *
                     const int32_t *qbegin, const int32_t *ints, double *reals, double *ws,
                     int iters, int32_t *counters, int32_t *gang_ctr, int32_t *status, int max_m,
                     int max_N, int max_d, int max_deg, int grid, int block, int eval_waves,
-                    int64_t *path_clock, void *stream);
+                    int64_t *path_clock, int64_t *phase_clock, void *stream);
+
+/* Section 6's protocol (as md_newton_protocol) for every path of a batch in
+ * one persistent launch, with per-path decisions taken on the device: each
+ * path runs the listed degrees that are at most its own d, each from its
+ * start point (coefficient 0 of its x on entry), with steps until
+ * |dx_{d_j}| <= tol (from step min_steps on) or maxit[j] steps, and stops
+ * after a degree that ends with |dx_{d_j}| above `diverge` (MD_ST_DIVERGED
+ * for that path).  A gang's members share each decision through the path's
+ * workspace.  Carries double to quad double (max_m <= 4).  Arguments as
+ * md_newton_batch, except: proto (host): the protocol; each path's
+ * workspace slice holds md_workspace_bytes(MD_FN_PROTOCOL, m, N, n, d, M,
+ * max_deg) bytes; x ends with the series of the path's last degree that ran
+ * (zero above it); proto_iters: device int32[npaths*ndeg], the steps per
+ * degree (0 when not run); proto_norms: device double[npaths*ndeg*10], the
+ * last |dx_{d_j}| of each degree as up to 10 limbs (zeros beyond m and for
+ * degrees not run).  The dx_norm slots of the paths are not written. */
+typedef struct md_protocol {
+  int32_t ndeg;                              /* 1..MD_PROTOCOL_MAX_DEGREES */
+  int32_t min_steps;                         /* >= 1 */
+  int32_t degrees[MD_PROTOCOL_MAX_DEGREES];  /* increasing, >= 0 */
+  int32_t maxit[MD_PROTOCOL_MAX_DEGREES];    /* 0..10000 */
+  double tol, diverge;                       /* >= 0, > 0 */
+} md_protocol;
+
+int md_newton_batch_protocol(int npaths, const md_path *paths, int njobs, const int32_t *jobs,
+                             int nq, const int32_t *qbegin, const int32_t *ints, double *reals,
+                             double *ws, const md_protocol *proto, int32_t *counters,
+                             int32_t *gang_ctr, int32_t *status, int max_m, int max_N, int max_d,
+                             int max_deg, int grid, int block, int eval_waves, int32_t *proto_iters,
+                             double *proto_norms, void *stream);
 
 /* Writes, for each of nblocks workgroups of a small launch, the accelerator
  * die (XCC) it ran on: device int32[nblocks].  The queues of

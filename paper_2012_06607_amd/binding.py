@@ -450,9 +450,10 @@ class BatchedPaths:
     int32 arena), coefficients, series and update norms (one float64 arena),
     and private workspaces (one float64 arena, 256-byte aligned slices).
     `paths` is a list of (System, x planes (2, m, d+1, n)); `order` (job
-    order) defaults to longest first by the analytic operation count."""
+    order) defaults to longest first by the analytic operation count;
+    protocol: size the workspaces for md_newton_batch_protocol."""
 
-    def __init__(self, paths, device="cuda", order=None):
+    def __init__(self, paths, device="cuda", order=None, protocol: bool = False):
         from . import opcount as OC
         ints, reals = [], []
         n_int, n_real, n_ws = 0, 0, 0
@@ -492,7 +493,8 @@ class BatchedPaths:
                 t[name] = n_real
                 reals.append(arr)
                 n_real += arr.size
-            wsb = lib().md_workspace_bytes(MD_FN_NEWTON, m, sysm.N, sysm.n, d, sysm.M, sysm.max_deg)
+            wsb = lib().md_workspace_bytes(MD_FN_PROTOCOL if protocol else MD_FN_NEWTON, m, sysm.N,
+                                           sysm.n, d, sysm.M, sysm.max_deg)
             if wsb == 0:
                 raise MdError(f"path {p}: unsupported sizes")
             t["ws"] = n_ws
@@ -500,6 +502,7 @@ class BatchedPaths:
             cost[p] = OC.newton_step(sysm, d, m).table_ops(m)
             self.meta.append((m, sysm.N, sysm.n, d))
         dev = torch.device(device)
+        self.protocol = protocol
         self.npaths = len(paths)
         self.table = table
         self.cost = cost
@@ -603,16 +606,19 @@ def md_batch_lds_bytes(max_m: int, max_d: int, max_deg: int, eval_waves: int) ->
 
 def md_newton_batch(batch: BatchedPaths, iters: int, grid: int | None = None,
                     eval_waves: int | None = None, stream=None, block: int = 256,
-                    path_clock: torch.Tensor | None = None):
+                    path_clock: torch.Tensor | None = None,
+                    phase_clock: torch.Tensor | None = None):
     """`iters` Newton steps on every path of the batch in one persistent
     launch, with the batch's job schedule (BatchedPaths.set_schedule; the
     library resets the counters on the stream first).  path_clock: optional
     int64 device tensor (npaths, 2) that receives each path's start and end
-    on the device wall clock."""
+    on the device wall clock; phase_clock: optional int64 (npaths, 8),
+    zeroed, receives the ticks each path spent per phase (evaluation, sums,
+    QR, R^{-1} Q^H, stages, update)."""
     L = lib()
     P, i32 = ctypes.c_void_p, ctypes.c_int
     L.md_newton_batch.argtypes = [i32, P, i32, P, i32, P, P, P, P, i32, P, P, P, i32, i32, i32,
-                                  i32, i32, i32, i32, P, P]
+                                  i32, i32, i32, i32, P, P, P]
     L.md_newton_batch.restype = ctypes.c_int
     if batch.max_m >= 5 and block != 256:
         if block == 512 and eval_waves is None:
@@ -629,6 +635,8 @@ def md_newton_batch(batch: BatchedPaths, iters: int, grid: int | None = None,
         grid = props.multi_processor_count
     if path_clock is not None and tuple(path_clock.shape) != (batch.npaths, 2):
         raise MdError("path_clock must have shape (npaths, 2)")
+    if phase_clock is not None and tuple(phase_clock.shape) != (batch.npaths, 8):
+        raise MdError("phase_clock must have shape (npaths, 8)")
     if grid < batch.nq * int(batch.gangs.max(initial=1)):
         raise MdError(f"grid={grid} too small for {batch.nq} queues with gangs of "
                       f"{int(batch.gangs.max(initial=1))}")
@@ -639,8 +647,67 @@ def md_newton_batch(batch: BatchedPaths, iters: int, grid: int | None = None,
                              _ptr(batch.counters, torch.int32), _ptr(batch.gang_ctr, torch.int32),
                              _ptr(batch.status, torch.int32), batch.max_m, batch.max_N,
                              batch.max_d, batch.max_deg, grid, block, eval_waves,
-                             _ptr(path_clock, torch.int64), _stream(stream)), "md_newton_batch")
+                             _ptr(path_clock, torch.int64), _ptr(phase_clock, torch.int64),
+                             _stream(stream)), "md_newton_batch")
     return batch
+
+
+class md_protocol(ctypes.Structure):
+    _fields_ = [("ndeg", ctypes.c_int32), ("min_steps", ctypes.c_int32),
+                ("degrees", ctypes.c_int32 * MD_PROTOCOL_MAX_DEGREES),
+                ("maxit", ctypes.c_int32 * MD_PROTOCOL_MAX_DEGREES),
+                ("tol", ctypes.c_double), ("diverge", ctypes.c_double)]
+
+
+def md_newton_batch_protocol(batch: BatchedPaths, degrees=(8, 16, 24, 32), maxit=(8, 8, 12, 16),
+                             tol: float = 1e-32, diverge: float = 1.0, min_steps: int = 2,
+                             grid: int | None = None, block: int = 512,
+                             eval_waves: int | None = None, stream=None):
+    """Section 6's protocol on every path of the batch in one persistent
+    launch (per-path decisions on the device).  The batch must have been
+    built with protocol=True.  Returns (iters int32 (npaths, ndeg), norms
+    float64 (npaths, ndeg, 10): |dx_d| per degree as limbs)."""
+    if not batch.protocol:
+        raise MdError("md_newton_batch_protocol: build the batch with protocol=True")
+    if batch.max_m > 4:
+        raise MdError("md_newton_batch_protocol: double to quad double paths only")
+    deg, mit = list(degrees), list(maxit)
+    if not 1 <= len(deg) <= MD_PROTOCOL_MAX_DEGREES or len(deg) != len(mit):
+        raise MdError("md_newton_batch_protocol: degrees and maxit must be equal-length lists")
+    pr = md_protocol()
+    pr.ndeg, pr.min_steps, pr.tol, pr.diverge = len(deg), int(min_steps), float(tol), float(diverge)
+    for j, (dj, mj) in enumerate(zip(deg, mit)):
+        pr.degrees[j], pr.maxit[j] = int(dj), int(mj)
+    L = lib()
+    P, i32 = ctypes.c_void_p, ctypes.c_int
+    L.md_newton_batch_protocol.argtypes = [i32, P, i32, P, i32, P, P, P, P,
+                                           ctypes.POINTER(md_protocol), P, P, P, i32, i32, i32,
+                                           i32, i32, i32, i32, P, P, P]
+    L.md_newton_batch_protocol.restype = ctypes.c_int
+    if eval_waves is None:
+        eval_waves = block // 64
+        while eval_waves > 1 and md_batch_lds_bytes(batch.max_m, batch.max_d, batch.max_deg,
+                                                     eval_waves) > md_device_lds_bytes():
+            eval_waves -= 1
+    if grid is None:
+        grid = torch.cuda.get_device_properties(batch.reals.device).multi_processor_count
+    if grid < batch.nq * int(batch.gangs.max(initial=1)):
+        raise MdError(f"grid={grid} too small for {batch.nq} queues with gangs of "
+                      f"{int(batch.gangs.max(initial=1))}")
+    iters = torch.zeros((batch.npaths, len(deg)), dtype=torch.int32, device=batch.device)
+    norms = torch.zeros((batch.npaths, len(deg), 10), dtype=torch.float64, device=batch.device)
+    _check(L.md_newton_batch_protocol(batch.npaths, _ptr(batch.paths_dev, torch.uint8),
+                                      batch.njobs, _ptr(batch.jobs, torch.int32), batch.nq,
+                                      _ptr(batch.qbegin, torch.int32),
+                                      _ptr(batch.ints, torch.int32), _ptr(batch.reals),
+                                      _ptr(batch.ws), ctypes.byref(pr),
+                                      _ptr(batch.counters, torch.int32),
+                                      _ptr(batch.gang_ctr, torch.int32),
+                                      _ptr(batch.status, torch.int32), batch.max_m, batch.max_N,
+                                      batch.max_d, batch.max_deg, grid, block, eval_waves,
+                                      _ptr(iters, torch.int32), _ptr(norms), _stream(stream)),
+           "md_newton_batch_protocol")
+    return iters, norms
 
 
 _dies = {}

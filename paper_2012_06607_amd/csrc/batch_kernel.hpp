@@ -160,15 +160,35 @@ __device__ __forceinline__ void qr_gang(QrShared<M> &sh, int N, int n, int seg,
   }
 }
 
+// Protocol control of one path's steps at one truncation degree (the
+// batched form of Section 6's protocol): after each step member 0 compares
+// |dx_d| with tol (from step min_steps on) and publishes the decision in
+// `word` (the path's workspace) before the step's closing gang barrier, so
+// every member reads the same decision.  `steps` and `norm` receive the
+// steps taken and the last |dx_d| (member 0).
 template <int M>
-__device__ __forceinline__ void newton_path(const md_path &p, int iters, const int32_t *__restrict__ ints,
+struct StepCtl {
+  bool on = false;
+  int min_steps = 1;
+  double tol = 0.0;
+  int32_t *word = nullptr;
+  int *steps = nullptr;
+  mdr<M> *norm = nullptr;
+};
+
+// `iters` Newton steps on the path at truncation degree d (<= p.d) with the
+// series x (planes (2, m, d+1, n)), or fewer under a StepCtl.
+template <int M>
+__device__ __forceinline__ void newton_steps(const md_path &p, int d, double *__restrict__ x,
+                            bool store_norm, int iters, const int32_t *__restrict__ ints,
                             double *__restrict__ reals, double *__restrict__ wsb,
                             int32_t *__restrict__ status, int path, double *lds_raw,
-                            int eval_waves, int member, int G, int32_t *gang_ctr) {
+                            int eval_waves, int member, int G, int32_t *gang_ctr,
+                            int64_t *pclk, int &st, int &round, const StepCtl<M> &ctl) {
   __shared__ QrShared<M> qsh;
   __shared__ mdr<M> msh[16];  // one per wave, up to 1024 threads
   __shared__ int term_next;   // the workgroup's term queue (one workgroup per path)
-  const int N = p.N, n = p.n, d = p.d, L = d + 1;
+  const int N = p.N, n = p.n, L = d + 1;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int wave = tid / WAVE, nwaves = nt / WAVE;
   const NewtonLayout lay(M, N, n, d, p.M, p.max_deg);
@@ -183,7 +203,6 @@ __device__ __forceinline__ void newton_path(const md_path &p, int iters, const i
   double *r = reinterpret_cast<double *>(w + lay.off_solve + sl.off_r);
   double *W = reinterpret_cast<double *>(w + lay.off_solve + sl.off_G);
   double *invd = W + size_t(2) * M * n * N;
-  double *x = reals + p.x;
   int32_t *gang_terms = reinterpret_cast<int32_t *>(w + lay.off_ctr);
   EvalArgs a;
   a.d = d;
@@ -231,7 +250,20 @@ __device__ __forceinline__ void newton_path(const md_path &p, int iters, const i
   const int per_wave = term_lds_series(p.max_deg) * L;
   mdc<M> *lds = reinterpret_cast<mdc<M> *>(lds_raw);
   const long Ex = long(L) * n, Er = long(L) * N;
-  int st = 0, round = 0;
+  (void)Er;
+  // phase clocks (optional): member 0's thread 0 adds the device wall-clock
+  // time of each phase of every step to pclk[0..6] (evaluation, Jacobian
+  // sums, QR, R^{-1} Q^H, stages, update); the phases end at barriers, so
+  // the gang's members are done too
+  const bool timing = pclk && member == 0 && tid == 0;
+  int64_t tprev = timing ? wall_clock64() : 0;
+  auto phase = [&](int ph) {
+    if (timing) {
+      const int64_t t = wall_clock64();
+      pclk[ph] += t - tprev;
+      tprev = t;
+    }
+  };
   auto gsync = [&] {
     if (G > 1) gang_barrier(gang_ctr, G, round, st);
     else __syncthreads();
@@ -260,6 +292,7 @@ __device__ __forceinline__ void newton_path(const md_path &p, int iters, const i
         eval_term_wave<M>(a, tau, rgrp, lds + wave * per_wave, [] { wave_sync(); });
     }
     gsync();
+    phase(0);
     // the queues start again at zero for the next step (read after later
     // barriers, gang barriers for the gang's queue)
     if (tid == 0) term_next = 0;
@@ -267,6 +300,7 @@ __device__ __forceinline__ void newton_path(const md_path &p, int iters, const i
     for (long g0 = long(member) * nt + wave * WAVE; g0 < long(L) * N; g0 += long(G) * nt)
       eval_accumulate_wave<M>(a, g0, r, [] { wave_sync(); });
     gsync();
+    phase(1);
     // QR of A_0 (the k = 0 block of A), its columns over all members of a
     // gang, then W = R^{-1} (Q^H)_{0:n}, columns over all members
     if (G > 1) {
@@ -277,11 +311,13 @@ __device__ __forceinline__ void newton_path(const md_path &p, int iters, const i
       inv_diag_range<M>(tid, nt, N, n, QR, invd, st);
     }
     gsync();
+    phase(2);
     for (int base = member * nslots_p; base < N; base += G * nslots_p) {
       const int c = base + slot_p;
       pinv_column<M, 4>(c < N, c, N, n, seg_p, QR, vd, beta, invd, W);
     }
     gsync();
+    phase(3);
     // staggered substitution: every member forms dx_k, the updates of the
     // later right hand sides are split over the members
     for (int k = 0; k <= d; ++k) {
@@ -302,27 +338,121 @@ __device__ __forceinline__ void newton_path(const md_path &p, int iters, const i
         gsync();
       }
     }
-    if (member != 0) {
+    phase(4);
+    if (member == 0) {
+      // x += dx and the size of the update (member 0)
+      mdr<M> bd = md_zero<M>(), ba = md_zero<M>();
+      for (long e = tid; e < Ex; e += nt) {
+        const mdc<M> u = cload<M>(dx, Ex, e);
+        cstore<M>(x, Ex, e, c_add<M>(cload<M>(x, Ex, e), u));
+        const mdr<M> a2 = c_abs2<M>(u);
+        if (md_less<M>(ba, a2)) ba = a2;
+        if (e >= long(d) * n && md_less<M>(bd, a2)) bd = a2;
+      }
+      bd = wg_max<M>(bd, msh);
+      ba = wg_max<M>(ba, msh);
+      if (tid == 0 && store_norm && it == iters - 1) {
+        rstore<M>(reals + p.dx_norm, 2, 0, md_sqrt<M>(bd));
+        rstore<M>(reals + p.dx_norm, 2, 1, md_sqrt<M>(ba));
+      }
+      if (ctl.on && tid == 0) {
+        // this step's stopping decision, for every member of the gang
+        const mdr<M> nd = md_sqrt<M>(bd);
+        *ctl.norm = nd;
+        *ctl.steps = it + 1;
+        const bool done = it + 1 >= ctl.min_steps && !md_less<M>(md_from<M>(ctl.tol), nd);
+        __hip_atomic_store(ctl.word, done ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    if (ctl.on) {
+      gsync();  // the decision is visible to every member
+      const int stop = __builtin_amdgcn_readfirstlane(
+          __hip_atomic_load(ctl.word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      phase(5);
+      if (stop) break;
+    } else {
       if (it + 1 < iters) gsync();
-      continue;
+      else __syncthreads();
+      phase(5);
     }
-    // x += dx and the size of the update (member 0)
-    mdr<M> bd = md_zero<M>(), ba = md_zero<M>();
-    for (long e = tid; e < Ex; e += nt) {
-      const mdc<M> u = cload<M>(dx, Ex, e);
-      cstore<M>(x, Ex, e, c_add<M>(cload<M>(x, Ex, e), u));
-      const mdr<M> a2 = c_abs2<M>(u);
-      if (md_less<M>(ba, a2)) ba = a2;
-      if (e >= long(d) * n && md_less<M>(bd, a2)) bd = a2;
+  }
+}
+
+// One path: `iters` Newton steps at the path's degree, or, with a protocol,
+// Section 6's protocol over its degrees (each degree from the start point,
+// steps until |dx_d| <= tol from step min_steps on or the degree's limit,
+// the later degrees skipped once a degree ends above the divergence bound;
+// the series of the last degree run ends in x, zero above that degree).
+template <int M>
+__device__ __forceinline__ void newton_path(const md_path &p, int iters, const int32_t *__restrict__ ints,
+                            double *__restrict__ reals, double *__restrict__ wsb,
+                            int32_t *__restrict__ status, int path, double *lds_raw,
+                            int eval_waves, int member, int G, int32_t *gang_ctr,
+                            int64_t *pclk, const md_protocol *proto, int32_t *proto_iters,
+                            double *proto_norms) {
+  int st = 0, round = 0;
+  const int tid = threadIdx.x;
+  double *x = reals + p.x;
+  if (!proto) {
+    newton_steps<M>(p, p.d, x, true, iters, ints, reals, wsb, status, path, lds_raw, eval_waves,
+                    member, G, gang_ctr, pclk, st, round, StepCtl<M>{});
+  } else {
+    const ProtocolLayout pl(M, p.N, p.n, p.d, p.M, p.max_deg);
+    char *w = reinterpret_cast<char *>(wsb + p.ws);
+    double *xj = reinterpret_cast<double *>(w + pl.off_x);
+    double *x0 = reinterpret_cast<double *>(w + pl.off_x0);
+    int32_t *words = reinterpret_cast<int32_t *>(w + pl.off_flags);
+    const int n = p.n, ndeg = proto->ndeg;
+    const long E0 = long(p.d + 1) * n;
+    auto gsync = [&] {
+      if (G > 1) gang_barrier(gang_ctr, G, round, st);
+      else __syncthreads();
+    };
+    // the start point, kept while x receives each degree's series
+    if (member == 0)
+      for (long e = tid; e < n; e += blockDim.x) cstore<M>(x0, n, e, cload<M>(x, E0, e));
+    gsync();
+    int stopped = 0;
+    for (int j = 0; j < ndeg; ++j) {
+      const int dj = proto->degrees[j];
+      const bool run = !stopped && dj <= p.d;
+      int steps = 0;
+      mdr<M> nd = md_zero<M>();
+      if (run) {
+        const long Ej = long(dj + 1) * n;
+        if (member == 0)
+          for (long e = tid; e < Ej; e += blockDim.x)
+            cstore<M>(xj, Ej, e, e < n ? cload<M>(x0, n, e) : c_zero<M>());
+        gsync();
+        StepCtl<M> ctl;
+        ctl.on = true;
+        ctl.min_steps = proto->min_steps;
+        ctl.tol = proto->tol;
+        ctl.word = words;
+        ctl.steps = &steps;
+        ctl.norm = &nd;
+        newton_steps<M>(p, dj, xj, false, proto->maxit[j], ints, reals, wsb, status, path,
+                        lds_raw, eval_waves, member, G, gang_ctr, pclk, st, round, ctl);
+        // the degree's series to x (member 0), and whether the next degrees run
+        if (member == 0) {
+          for (long e = tid; e < E0; e += blockDim.x)
+            cstore<M>(x, E0, e, e < Ej ? cload<M>(xj, Ej, e) : c_zero<M>());
+          if (tid == 0) {
+            const bool div = md_less<M>(md_from<M>(proto->diverge), nd);
+            __hip_atomic_store(words + 1, div ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (div) st |= MD_ST_DIVERGED;
+          }
+        }
+        gsync();
+        stopped = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(words + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      }
+      if (member == 0 && tid == 0) {
+        proto_iters[long(path) * ndeg + j] = run ? steps : 0;
+        for (int l = 0; l < 10; ++l)
+          proto_norms[(long(path) * ndeg + j) * 10 + l] = (run && l < M) ? nd.v[l] : 0.0;
+      }
     }
-    bd = wg_max<M>(bd, msh);
-    ba = wg_max<M>(ba, msh);
-    if (tid == 0 && it == iters - 1) {
-      rstore<M>(reals + p.dx_norm, 2, 0, md_sqrt<M>(bd));
-      rstore<M>(reals + p.dx_norm, 2, 1, md_sqrt<M>(ba));
-    }
-    if (it + 1 < iters) gsync();
-    else __syncthreads();
   }
   if (tid == 0) {
     if (st) atomicOr(status + path, st);
@@ -333,7 +463,7 @@ __device__ __forceinline__ void newton_path(const md_path &p, int iters, const i
 // BLOCK threads per workgroup; MS: 0 for the kernel of double to quad
 // double paths (m in 1..4), else the one limb count (5, 8 or 10) the
 // kernel carries (one translation unit each: these compile slowly).
-template <int BLOCK, int MS>
+template <int BLOCK, int MS, bool PROTO>
 __global__ void __launch_bounds__(BLOCK) k_newton_batch(int npaths, const md_path *__restrict__ paths,
                                                         const int32_t *__restrict__ jobs, int nq,
                                                         const int32_t *__restrict__ qbegin,
@@ -342,7 +472,9 @@ __global__ void __launch_bounds__(BLOCK) k_newton_batch(int npaths, const md_pat
                                                         double *__restrict__ wsb, int iters,
                                                         int32_t *counters, int32_t *gang_ctr,
                                                         int32_t *status, int eval_waves,
-                                                        int64_t *clk) {
+                                                        int64_t *clk, int64_t *phase_clk,
+                                                        md_protocol proto, int32_t *proto_iters,
+                                                        double *proto_norms) {
   extern __shared__ double lds_raw[];
   __shared__ int sh_job;
   const int q = nq == 1 ? 0 : xcc_id() % nq;
@@ -372,14 +504,15 @@ __global__ void __launch_bounds__(BLOCK) k_newton_batch(int npaths, const md_pat
     if (ok) {
       if (clk && threadIdx.x == 0 && member == 0) clk[2 * path] = wall_clock64();
       int32_t *gc = gang_ctr + path;
+      int64_t *pclk = phase_clk ? phase_clk + 8 * long(path) : nullptr;
       if constexpr (MS != 0) {
-        newton_path<MS>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc);
+        newton_path<MS>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc, pclk, PROTO ? &proto : nullptr, proto_iters, proto_norms);
       } else {
         switch (p.m) {
-          case 1: newton_path<1>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc); break;
-          case 2: newton_path<2>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc); break;
-          case 3: newton_path<3>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc); break;
-          default: newton_path<4>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc); break;
+          case 1: newton_path<1>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc, pclk, PROTO ? &proto : nullptr, proto_iters, proto_norms); break;
+          case 2: newton_path<2>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc, pclk, PROTO ? &proto : nullptr, proto_iters, proto_norms); break;
+          case 3: newton_path<3>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc, pclk, PROTO ? &proto : nullptr, proto_iters, proto_norms); break;
+          default: newton_path<4>(p, iters, ints, reals, wsb, status, path, lds_raw, eval_waves, member, G, gc, pclk, PROTO ? &proto : nullptr, proto_iters, proto_norms); break;
         }
       }
     }
@@ -401,12 +534,20 @@ void launch_newton_batch_lo(int block, int grid, size_t lds, hipStream_t s, int 
                             const md_path *paths, const int32_t *jobs, int nq,
                             const int32_t *qbegin, const int32_t *ints, double *reals, double *ws,
                             int iters, int32_t *counters, int32_t *gang_ctr, int32_t *status,
-                            int eval_waves, int64_t *clk);
+                            int eval_waves, int64_t *clk, int64_t *phase_clk);
+// the protocol form of the double- to quad-double kernel (batch_proto.hip)
+void launch_newton_batch_proto(int block, int grid, size_t lds, hipStream_t s, int npaths,
+                               const md_path *paths, const int32_t *jobs, int nq,
+                               const int32_t *qbegin, const int32_t *ints, double *reals,
+                               double *ws, int32_t *counters, int32_t *gang_ctr, int32_t *status,
+                               int eval_waves, int64_t *clk, int64_t *phase_clk,
+                               const md_protocol &proto, int32_t *proto_iters,
+                               double *proto_norms);
 #define MDS_BATCH_WIDE_LAUNCH(NAME)                                                              \
   void NAME(int grid, size_t lds, hipStream_t s, int npaths, const md_path *paths,              \
             const int32_t *jobs, int nq, const int32_t *qbegin, const int32_t *ints,            \
             double *reals, double *ws, int iters, int32_t *counters, int32_t *gang_ctr,         \
-            int32_t *status, int eval_waves, int64_t *clk)
+            int32_t *status, int eval_waves, int64_t *clk, int64_t *phase_clk)
 MDS_BATCH_WIDE_LAUNCH(launch_newton_batch_m5);
 MDS_BATCH_WIDE_LAUNCH(launch_newton_batch_m8);
 MDS_BATCH_WIDE_LAUNCH(launch_newton_batch_m10);

@@ -6,9 +6,9 @@
 namespace mds {
 
 MDS_BATCH_WIDE_LAUNCH(launch_newton_batch_m10) {
-  k_newton_batch<256, 10><<<dim3(grid), dim3(256), lds, s>>>(
+  k_newton_batch<256, 10, false><<<dim3(grid), dim3(256), lds, s>>>(
       npaths, paths, jobs, nq, qbegin, ints, reals, ws, iters, counters, gang_ctr, status,
-      eval_waves, clk);
+      eval_waves, clk, phase_clk, md_protocol{}, nullptr, nullptr);
 }
 
 }  // namespace mds

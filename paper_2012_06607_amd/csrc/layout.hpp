@@ -87,16 +87,17 @@ struct AdjointLayout {
 
 // Newton protocol over increasing truncation degrees: a Newton step's
 // buffers sized for the largest degree, the iterate of the current degree
-// ((dmax+1) x n at most), the step's update norms (m, 2) and the flags
-// (running, stopped).
+// ((dmax+1) x n at most), the step's update norms (m, 2), the start point
+// (n; kept by the batched form) and the flags (running, stopped).
 struct ProtocolLayout {
   NewtonLayout nl;
-  size_t off_x, off_nrm, off_flags, bytes;
+  size_t off_x, off_nrm, off_x0, off_flags, bytes;
   __host__ __device__ ProtocolLayout(int m, int N, int n, int dmax, int M, int max_deg)
       : nl(m, N, n, dmax, M, max_deg) {
     off_x = nl.bytes;
     off_nrm = off_x + align256(sizeof(double) * 2 * m * size_t(dmax + 1) * n);
-    off_flags = off_nrm + align256(sizeof(double) * m * 2);
+    off_x0 = off_nrm + align256(sizeof(double) * m * 2);
+    off_flags = off_x0 + align256(sizeof(double) * 2 * m * size_t(n));
     bytes = off_flags + 256;
   }
 };

@@ -114,7 +114,7 @@ def test_batch_host_checks(lib):
     P = ctypes.c_void_p
     i = ctypes.c_int
     lib.md_newton_batch.argtypes = [i, P, i, P, i, P, P, P, P, i, P, P, P, i, i, i, i, i, i, i,
-                                    P, P]
+                                    P, P, P]
     lib.md_batch_lds_bytes.argtypes = [i] * 4
     lib.md_batch_lds_bytes.restype = ctypes.c_size_t
     fake = P(4096)
@@ -123,7 +123,7 @@ def test_batch_host_checks(lib):
              block=256, ew=4, paths=fake):
         return lib.md_newton_batch(npaths, paths, njobs, fake, nq, fake, fake, fake, fake, iters,
                                    fake, fake, fake, max_m, max_N, max_d, max_deg, grid, block, ew,
-                                   None, None)
+                                   None, None, None)
     # limb counts outside both batched kernels are rejected on the host, and
     # the penta to deca double kernel runs 256-thread workgroups only
     assert call(max_m=6) == 1
@@ -176,3 +176,36 @@ def test_noalloc_host_checks(lib):
     assert lib.md_newton_step_noalloc(2, 8, ctypes.byref(small), None, None, None, None) == 3
     bad = _System(4, 8, 80, 1, 3, 4096, 4096, 4096, 4096)
     assert lib.md_newton_step_noalloc(2, 8, ctypes.byref(bad), fake, None, None, None) == 2
+
+
+def test_batch_protocol_host_checks(lib):
+    import paper_2012_06607_amd.binding as Bd
+    P = ctypes.c_void_p
+    i = ctypes.c_int
+    lib.md_newton_batch_protocol.argtypes = [i, P, i, P, i, P, P, P, P,
+                                             ctypes.POINTER(Bd.md_protocol), P, P, P, i, i, i, i,
+                                             i, i, i, P, P, P]
+    lib.md_last_error.restype = ctypes.c_char_p
+    fake = P(4096)
+
+    def proto(degrees=(8, 16), maxit=(8, 8), min_steps=2, tol=1e-32, diverge=1.0):
+        pr = Bd.md_protocol()
+        pr.ndeg, pr.min_steps, pr.tol, pr.diverge = len(degrees), min_steps, tol, diverge
+        for j, (d, mi) in enumerate(zip(degrees, maxit)):
+            pr.degrees[j], pr.maxit[j] = d, mi
+        return pr
+
+    def call(pr, max_m=4, npaths=2, out=fake):
+        return lib.md_newton_batch_protocol(npaths, fake, 2, fake, 1, fake, fake, fake, fake,
+                                            ctypes.byref(pr) if pr is not None else None, fake,
+                                            fake, fake, max_m, 16, 16, 3, 16, 256, 4, out, out,
+                                            None)
+    assert call(None) == 3
+    assert call(proto(degrees=(16, 8))) == 1          # not increasing
+    assert call(proto(min_steps=0)) == 1
+    assert call(proto(tol=-1.0)) == 1
+    assert call(proto(diverge=0.0)) == 1
+    assert call(proto(), max_m=8) == 1                # double to quad double only
+    assert b"quad double" in lib.md_last_error()
+    assert call(proto(), out=None) == 3               # outputs needed
+    assert call(proto(), npaths=0) == 0               # empty batch
