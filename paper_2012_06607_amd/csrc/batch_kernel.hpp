@@ -302,7 +302,8 @@ __device__ __forceinline__ void newton_steps(const md_path &p, int d, double *__
     gsync();
     phase(1);
     // QR of A_0 (the k = 0 block of A), its columns over all members of a
-    // gang, then W = R^{-1} (Q^H)_{0:n}, columns over all members
+    // gang, then W = R^{-1} (Q^H)_{0:n}: the rows of (Q^H)_{0:n}, then the
+    // back substitution by columns, both over all members
     if (G > 1) {
       qr_gang<M, 4>(qsh, N, n, seg_q, A, long(L) * N * n, QR, vd, beta, st, member, G, gsync);
       if (member == 0) inv_diag_range<M>(tid, nt, N, n, QR, invd, st);
@@ -312,9 +313,20 @@ __device__ __forceinline__ void newton_steps(const md_path &p, int d, double *__
     }
     gsync();
     phase(2);
+    {
+      // the rows of (Q^H)_{0:n}: row r costs r + 1 reflectors, so the rows
+      // go out longest first and snaking over the slots of all members,
+      // which evens out every slot's total
+      const int T = G * nslots_p, gs = member * nslots_p + slot_p;
+      for (int k = 0; k * T < n; ++k) {
+        const int u = k * T + ((k & 1) ? T - 1 - gs : gs);
+        q_row<M, 4>(u < n, n - 1 - u, N, n, seg_p, QR, vd, beta, W);
+      }
+    }
+    gsync();
     for (int base = member * nslots_p; base < N; base += G * nslots_p) {
       const int c = base + slot_p;
-      pinv_column<M, 4>(c < N, c, N, n, seg_p, QR, vd, beta, invd, W);
+      backsub_column<M, 4>(c < N, c, N, n, seg_p, QR, invd, W);
     }
     gsync();
     phase(3);

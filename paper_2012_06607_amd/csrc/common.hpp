@@ -54,6 +54,15 @@ __device__ __forceinline__ bool gate_closed(const int32_t *gate) {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
 
+// The largest v over the wave, the same on every lane (all lanes active).
+__device__ __forceinline__ int wave_max_int(int v) {
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    const int t = __shfl_xor(v, o, WAVE);
+    v = v > t ? v : t;
+  }
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
 template <int M>
 __device__ __forceinline__ mdr<M> shfl_down_r(const mdr<M> &a, int off) {
   mdr<M> z;

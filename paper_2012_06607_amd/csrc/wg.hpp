@@ -441,6 +441,118 @@ __device__ __forceinline__ void pinv_column(bool live, int c, int N, int n, int 
   }
 }
 
+// The same W in two passes with less work.  Row r of (Q^H)_{0:n} is the
+// conjugate of column r of Q, and Q e_r = H_0 H_1 ... H_r e_r because H_j
+// (zero above row j) leaves e_r alone for j > r: r + 1 reflectors instead of
+// n.  q_row forms that row (one segment, lanes own entries lis, lis+seg,
+// ...; reflectors r, r-1, ..., 0) into W's buffer; after a barrier
+// backsub_column turns column c of it into column c of W = R^{-1} (Q^H)_{0:n}
+// in place.  Reflector j's rows are read where used (twice, through L1);
+// the loops over a lane's entries are unrolled, so g stays in registers.
+template <int M, int RPL>
+__device__ __forceinline__ void q_row(bool live, int r, int N, int n, int seg,
+                                      const double *__restrict__ QR,
+                                      const double *__restrict__ vdiag,
+                                      const double *__restrict__ beta, double *__restrict__ W) {
+  const long E = long(N) * n;
+  const long EW = long(n) * N;
+  const int lane = lane_id();
+  const int lis = lane & (seg - 1);
+  auto vrow = [&](int j, int i, const mdc<M> &v0) __attribute__((always_inline)) {
+    return i == j ? v0 : cload<M>(QR, E, long(i) * n + j);
+  };
+  mdc<M> g[RPL];
+  {
+    // H_r e_r = e_r - beta_r conj(v_r[r]) v_r
+    const mdc<M> v0 = live ? cload<M>(vdiag, n, r) : c_zero<M>();
+    const mdc<M> bw = c_mulr<M>(c_conj<M>(v0), live ? rload<M>(beta, n, r) : md_zero<M>());
+    mdc<M> one = c_zero<M>();
+    one.re = md_from<M>(1.0);
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int i = lis + q * seg;
+      g[q] = c_zero<M>();
+      if (live && i >= r && i < N)
+        g[q] = c_sub<M>(i == r ? one : c_zero<M>(), c_mul<M>(bw, vrow(r, i, v0)));
+    }
+  }
+  // the wave runs the longest row's steps; a segment works in steps j < r
+  const int rmax = wave_max_int(live ? r : 0);
+  for (int j = rmax - 1; j >= 0; --j) {
+    const bool act = live && j < r;
+    const mdc<M> v0 = act ? cload<M>(vdiag, n, j) : c_zero<M>();
+    const mdr<M> bet = act ? rload<M>(beta, n, j) : md_zero<M>();
+    mdc<M> w = c_zero<M>();
+    bool first = true;
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int i = lis + q * seg;
+      if (act && i >= j && i < N) {
+        const mdc<M> t = c_mul<M>(c_conj<M>(vrow(j, i, v0)), g[q]);
+        w = first ? t : c_add<M>(w, t);
+        first = false;
+      }
+    }
+    w = seg_reduce_c<M>(w, seg);
+    w = shfl_c<M>(w, lane & ~(seg - 1));
+    const mdc<M> bw = c_mulr<M>(w, bet);
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int i = lis + q * seg;
+      if (act && i >= j && i < N) g[q] = c_sub<M>(g[q], c_mul<M>(bw, vrow(j, i, v0)));
+    }
+  }
+  if (live) {
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int i = lis + q * seg;
+      if (i < N) cstore<M>(W, EW, long(r) * N + i, c_conj<M>(g[q]));
+    }
+  }
+}
+
+// Column c of W = R^{-1} Y in place, Y = (Q^H)_{0:n} as q_row left it (lanes
+// own rows lis, lis+seg, ... < n): the back substitution with the row owner
+// multiplying by 1/R_ii and broadcasting.
+template <int M, int RPL>
+__device__ __forceinline__ void backsub_column(bool live, int c, int N, int n, int seg,
+                                               const double *__restrict__ QR,
+                                               const double *__restrict__ invd,
+                                               double *__restrict__ W) {
+  const long E = long(N) * n;
+  const long EW = long(n) * N;
+  const int lane = lane_id();
+  const int lis = lane & (seg - 1);
+  mdc<M> g[RPL];
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    const int i = lis + q * seg;
+    g[q] = (live && i < n) ? cload<M>(W, EW, long(i) * N + c) : c_zero<M>();
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    const int owner = i & (seg - 1), ro = i / seg;
+    mdc<M> xi = c_zero<M>();
+#pragma unroll
+    for (int q = 0; q < RPL; ++q)
+      if (live && q == ro && lis == owner) xi = c_mul<M>(g[q], cload<M>(invd, n, i));
+    xi = shfl_c<M>(xi, (lane & ~(seg - 1)) + owner);
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int l = lis + q * seg;
+      if (!live) continue;
+      if (l == i) g[q] = xi;
+      else if (l < i) g[q] = c_sub<M>(g[q], c_mul<M>(cload<M>(QR, E, long(l) * n + i), xi));
+    }
+  }
+  if (live) {
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int i = lis + q * seg;
+      if (i < n) cstore<M>(W, EW, long(i) * N + c, g[q]);
+    }
+  }
+}
+
 // x = R^{-1} (Q^H b)_{0:n} for one right-hand side b (N entries) by one
 // segment: b's rows go to the lanes as in pinv_column, the n reflectors are
 // applied in order, then the back substitution with the row owner
