@@ -134,6 +134,19 @@ def test_convolve_bit_exact(B, m, count, d):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("m,count,d", ((10, 1, 400), (2, 2, 400), (2, 70000, 0), (4, 1, 1)))
+def test_convolve_long_series_and_many_tasks(B, m, count, d):
+    # deca double at d = 400 does not fit in LDS (the one-thread-per-pair
+    # form); 70000 one-coefficient series are more workgroup tasks than the
+    # grid holds (the workgroups loop)
+    g = I.rng(954, m, count, d)
+    x = I.unit_complex(g, m, count, d + 1)
+    y = I.unit_complex(g, m, count, d + 1)
+    want = oracle.convolve(x, y)
+    got = host(B.md_series_convolve(dev(x), dev(y)))
+    assert np.array_equal(got, want)
+
+
 def test_convolve_empty(B):
     x = torch.zeros((2, 2, 0, 9), dtype=torch.float64, device="cuda")
     z = B.md_series_convolve(x, x)
