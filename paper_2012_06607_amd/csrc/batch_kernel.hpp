@@ -113,7 +113,7 @@ __device__ __forceinline__ void qr_gang(QrShared<M> &sh, int N, int n, int seg,
     cstore<M>(QR, E, e, cload<M>(A0, A0E, e));
   gsync();
   for (int j = -1; j < n; ++j) {
-    constexpr bool HOLD = RPL < 4;
+    constexpr bool HOLD = RPL < 4 || M <= 2;
     mdc<M> vi[RPL], anew[RPL];
     mdc<M> v0 = c_zero<M>();
     mdr<M> bet = md_zero<M>();
@@ -341,11 +341,32 @@ __device__ __forceinline__ void newton_steps(const md_path &p, int d, double *__
       if (k < d) {
         const long rows = long(d - k) * N;
         const int seg_up = stage_seg(n, rows);
-        const int spw_u = WAVE / seg_up, nslots_u = nwaves * spw_u;
-        const int slot_u = wave * spw_u + lane_id() / seg_up;
-        for (long base = long(member) * nslots_u; base < rows; base += long(G) * nslots_u) {
-          const long row = base + slot_u;
-          stage_update_row<M>(row < rows, row, k, N, n, d, seg_up, A, dx, r);
+        if constexpr (M >= 3) {
+          const int spw_u = WAVE / seg_up, nslots_u = nwaves * spw_u;
+          const int slot_u = wave * spw_u + lane_id() / seg_up;
+          for (long base = long(member) * nslots_u; base < rows; base += long(G) * nslots_u) {
+            const long row = base + slot_u;
+            stage_update_row<M>(row < rows, row, k, N, n, d, seg_up, A, dx, r);
+          }
+        } else {
+          // double and double double: the rows stream A_j through the
+          // vector caches, so each lane reads its (at most eight) entries of
+          // dx_k once per stage instead of once per row.  (Four entries of
+          // quad double per lane, with wider segments, measured slower: the
+          // registers are not there.)
+          const int spw_u = WAVE / seg_up, nslots_u = nwaves * spw_u;
+          const int slot_u = wave * spw_u + lane_id() / seg_up;
+          mdc<M> dxr[8];
+          const int lis = lane_id() & (seg_up - 1);
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const int l = lis + t * seg_up;
+            dxr[t] = l < n ? cload<M>(dx, Ex, long(k) * n + l) : c_zero<M>();
+          }
+          for (long base = long(member) * nslots_u; base < rows; base += long(G) * nslots_u) {
+            const long row = base + slot_u;
+            stage_update_row_reg<M, 8>(row < rows, row, k, N, n, d, seg_up, A, dxr, r);
+          }
         }
         gsync();
       }

@@ -262,9 +262,10 @@ __device__ __forceinline__ void qr_wg(QrShared<M> &sh, int N, int n, int seg, co
   __syncthreads();
   // step j = -1 only loads column 0 and forms reflector 0
   for (int j = -1; j < n; ++j) {
-    // with four or more rows per lane nothing is held across the rounds:
-    // the reflector and column rows are read where they are used
-    constexpr bool HOLD = RPL < 4;
+    // with four or more rows per lane nothing is held across the rounds
+    // (the reflector and column rows are read where they are used), except
+    // up to double double, whose rows fit in the registers
+    constexpr bool HOLD = RPL < 4 || M <= 2;
     mdc<M> vi[RPL], anew[RPL];
     mdc<M> v0 = c_zero<M>();
     mdr<M> bet = md_zero<M>();
@@ -484,11 +485,17 @@ __device__ __forceinline__ void q_row(bool live, int r, int N, int n, int seg,
     const mdr<M> bet = act ? rload<M>(beta, n, j) : md_zero<M>();
     mdc<M> w = c_zero<M>();
     bool first = true;
+    // up to double double the reflector's rows stay in registers for the
+    // second pass; wider numbers read them again (registers are short)
+    constexpr bool HOLDV = M <= 2;
+    mdc<M> vq[HOLDV ? RPL : 1];
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
       const int i = lis + q * seg;
       if (act && i >= j && i < N) {
-        const mdc<M> t = c_mul<M>(c_conj<M>(vrow(j, i, v0)), g[q]);
+        const mdc<M> vv = vrow(j, i, v0);
+        if constexpr (HOLDV) vq[q] = vv;
+        const mdc<M> t = c_mul<M>(c_conj<M>(vv), g[q]);
         w = first ? t : c_add<M>(w, t);
         first = false;
       }
@@ -499,7 +506,10 @@ __device__ __forceinline__ void q_row(bool live, int r, int N, int n, int seg,
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
       const int i = lis + q * seg;
-      if (act && i >= j && i < N) g[q] = c_sub<M>(g[q], c_mul<M>(bw, vrow(j, i, v0)));
+      if (act && i >= j && i < N) {
+        if constexpr (HOLDV) g[q] = c_sub<M>(g[q], c_mul<M>(bw, vq[q]));
+        else g[q] = c_sub<M>(g[q], c_mul<M>(bw, vrow(j, i, v0)));
+      }
     }
   }
   if (live) {
@@ -679,6 +689,36 @@ __device__ __forceinline__ void stage_update_row(bool live, long row, int k, int
       s = first ? t : c_add<M>(s, t);
       first = false;
     }
+  s = seg_reduce_c<M>(s, seg);
+  if (live && lis == 0) {
+    const long e = long(k + j) * N + i;
+    cstore<M>(r, Er, e, c_sub<M>(cload<M>(r, Er, e), s));
+  }
+}
+
+// The same update with this lane's entries of dx_k already in registers
+// (dxr[t] = dx_k[lis + t*seg], t < NE; seg * NE >= n): the same products
+// and sums as stage_update_row, without reading dx_k again for every row.
+template <int M, int NE>
+__device__ __forceinline__ void stage_update_row_reg(bool live, long row, int k, int N, int n,
+                                                     int d, int seg, const double *__restrict__ A,
+                                                     const mdc<M> (&dxr)[NE],
+                                                     double *__restrict__ r) {
+  const long EA = long(d + 1) * N * n, Er = long(d + 1) * N;
+  const int lis = lane_id() & (seg - 1);
+  const int j = int(row / N) + 1;
+  const int i = int(row - long(j - 1) * N);
+  mdc<M> s = c_zero<M>();
+  bool first = true;
+#pragma unroll
+  for (int t = 0; t < NE; ++t) {
+    const int l = lis + t * seg;
+    if (live && l < n) {
+      const mdc<M> p = c_mul<M>(cload<M>(A, EA, (long(j) * N + i) * n + l), dxr[t]);
+      s = first ? p : c_add<M>(s, p);
+      first = false;
+    }
+  }
   s = seg_reduce_c<M>(s, seg);
   if (live && lis == 0) {
     const long e = long(k + j) * N + i;
