@@ -43,9 +43,9 @@ M1, N1, D1 = 4, 32, 16    # the single-path step
 # (--copy-mib 256).  Valid only for the kernel sources the counters were
 # taken on: dropped (null) when their hash differs.
 TRAFFIC = {
-    "k_newton_batch": {"fetch_kib": 66286975.675, "fetch_scale": 262144 / 131088.1875,
-                       "write_kib": 31638919.4875, "write_scale": 262144 / 262145.625,
-                       "sha256": "9df1b44cb3130cd5840bc56b228e9197524073d7eba76c42f4537520c12379ca",
+    "k_newton_batch": {"fetch_kib": 66524513.8625, "fetch_scale": 262144 / 131088.3125,
+                       "write_kib": 31880710.8, "write_scale": 262144 / 262144.625,
+                       "sha256": "e656748b5b420a2bb5d6457164b20b8f4524ae62440d00d9f88fd6ac86860dad",
                        "sources": ("batch.hip", "batch_kernel.hpp", "internal.hpp", "common.hpp",
                                    "md.hpp", "wg.hpp", "layout.hpp", "series.hpp")},
     "k_qr": {"fetch_kib": 102.375, "fetch_scale": 262144 / 131088.4375, "write_kib": 67.0,

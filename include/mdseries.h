@@ -329,7 +329,9 @@ typedef struct md_path {
   int64_t ws;
 } md_path;
 
-/* LDS bytes the batched kernel needs for its evaluation stage. */
+/* Dynamic LDS bytes the batched kernel needs: the evaluation's term series
+ * (2 max_m term_lds_series(max_deg) (max_d+1) eval_waves doubles), at least
+ * one dx_k of 64 unknowns (2 max_m 64 doubles); 0 for invalid arguments. */
 size_t md_batch_lds_bytes(int max_m, int max_d, int max_deg, int eval_waves);
 
 /* Runs `iters` Newton steps on each of `npaths` paths in one persistent

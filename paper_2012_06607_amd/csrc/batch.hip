@@ -62,8 +62,12 @@ using namespace mds;
 extern "C" size_t md_batch_lds_bytes(int max_m, int max_d, int max_deg, int eval_waves) {
   if (!(max_m >= 1 && max_m <= 4) && max_m != 5 && max_m != 8 && max_m != 10) return 0;
   if (max_d < 0 || max_deg < 0 || eval_waves < 1) return 0;
-  return sizeof(double) * 2 * size_t(max_m) * size_t(term_lds_series(max_deg)) * (max_d + 1) *
-         eval_waves;
+  // the evaluation's series, or a copy of one dx_k of up to 64 unknowns
+  // during the stages, whichever is larger
+  const size_t ev = sizeof(double) * 2 * size_t(max_m) * size_t(term_lds_series(max_deg)) *
+                    (max_d + 1) * eval_waves;
+  const size_t dxl = sizeof(double) * 2 * size_t(max_m) * WAVE;
+  return ev > dxl ? ev : dxl;
 }
 
 namespace {

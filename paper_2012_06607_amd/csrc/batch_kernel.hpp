@@ -249,6 +249,9 @@ __device__ __forceinline__ void newton_steps(const md_path &p, int d, double *__
   const int rgrp = eval_group(d);
   const int per_wave = term_lds_series(p.max_deg) * L;
   mdc<M> *lds = reinterpret_cast<mdc<M> *>(lds_raw);
+  // during the stages the evaluation's LDS holds a copy of dx_k (planes
+  // (2, M, n); md_batch_lds_bytes leaves room for n = 64)
+  double *lds_dx = reinterpret_cast<double *>(lds_raw);
   const long Ex = long(L) * n, Er = long(L) * N;
   (void)Er;
   // phase clocks (optional): member 0's thread 0 adds the device wall-clock
@@ -335,18 +338,28 @@ __device__ __forceinline__ void newton_steps(const md_path &p, int d, double *__
     for (int k = 0; k <= d; ++k) {
       for (int base = 0; base < n; base += nslots_x) {
         const int i = base + slot_x;
-        stage_dx_row<M>(i < n, i, k, N, n, d, seg_dx, W, r, dx, st);
+        stage_dx_row<M>(i < n, i, k, N, n, d, seg_dx, W, r, dx, st,
+                        (M == 3 || M == 4) ? lds_dx : nullptr);
       }
       __syncthreads();
       if (k < d) {
         const long rows = long(d - k) * N;
         const int seg_up = stage_seg(n, rows);
-        if constexpr (M >= 3) {
+        if constexpr (M >= 5) {
           const int spw_u = WAVE / seg_up, nslots_u = nwaves * spw_u;
           const int slot_u = wave * spw_u + lane_id() / seg_up;
           for (long base = long(member) * nslots_u; base < rows; base += long(G) * nslots_u) {
             const long row = base + slot_u;
             stage_update_row<M>(row < rows, row, k, N, n, d, seg_up, A, dx, r);
+          }
+        } else if constexpr (M >= 3) {
+          // triple and quad double: dx_k from its copy in LDS (each member
+          // formed all of it), not through the vector caches
+          const int spw_u = WAVE / seg_up, nslots_u = nwaves * spw_u;
+          const int slot_u = wave * spw_u + lane_id() / seg_up;
+          for (long base = long(member) * nslots_u; base < rows; base += long(G) * nslots_u) {
+            const long row = base + slot_u;
+            stage_update_row_lds<M>(row < rows, row, k, N, n, d, seg_up, A, lds_dx, r);
           }
         } else {
           // double and double double: the rows stream A_j through the

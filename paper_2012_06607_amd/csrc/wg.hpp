@@ -653,7 +653,7 @@ __host__ __device__ inline int dot_seg_throughput(int len) {
 template <int M>
 __device__ __forceinline__ void stage_dx_row(bool live, int i, int k, int N, int n, int d, int seg,
                              const double *__restrict__ W, const double *__restrict__ r,
-                             double *__restrict__ dx, int &st) {
+                             double *__restrict__ dx, int &st, double *dxl = nullptr) {
   const long EW = long(n) * N, Er = long(d + 1) * N, Ex = long(d + 1) * n;
   const int lis = lane_id() & (seg - 1);
   mdc<M> s = c_zero<M>();
@@ -667,6 +667,7 @@ __device__ __forceinline__ void stage_dx_row(bool live, int i, int k, int N, int
   s = seg_reduce_c<M>(s, seg);
   if (live && lis == 0) {
     cstore<M>(dx, Ex, long(k) * n + i, s);
+    if (dxl) cstore<M>(dxl, n, i, s);  // a copy of dx_k as planes (2, M, n), in LDS
     if (!c_finite<M>(s)) st |= MD_ST_NONFINITE;
   }
 }
@@ -686,6 +687,30 @@ __device__ __forceinline__ void stage_update_row(bool live, long row, int k, int
     for (int l = lis; l < n; l += seg) {
       const mdc<M> t = c_mul<M>(cload<M>(A, EA, (long(j) * N + i) * n + l),
                                 cload<M>(dx, Ex, long(k) * n + l));
+      s = first ? t : c_add<M>(s, t);
+      first = false;
+    }
+  s = seg_reduce_c<M>(s, seg);
+  if (live && lis == 0) {
+    const long e = long(k + j) * N + i;
+    cstore<M>(r, Er, e, c_sub<M>(cload<M>(r, Er, e), s));
+  }
+}
+
+// The same update with dx_k read from a copy in LDS (planes (2, M, n)).
+template <int M>
+__device__ __forceinline__ void stage_update_row_lds(bool live, long row, int k, int N, int n,
+                                                     int d, int seg, const double *__restrict__ A,
+                                                     const double *dxl, double *__restrict__ r) {
+  const long EA = long(d + 1) * N * n, Er = long(d + 1) * N;
+  const int lis = lane_id() & (seg - 1);
+  const int j = int(row / N) + 1;
+  const int i = int(row - long(j - 1) * N);
+  mdc<M> s = c_zero<M>();
+  bool first = true;
+  if (live)
+    for (int l = lis; l < n; l += seg) {
+      const mdc<M> t = c_mul<M>(cload<M>(A, EA, (long(j) * N + i) * n + l), cload<M>(dxl, n, l));
       s = first ? t : c_add<M>(s, t);
       first = false;
     }

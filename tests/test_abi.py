@@ -148,6 +148,9 @@ def test_batch_host_checks(lib):
     assert call(max_d=200, max_deg=4) == 2
     assert lib.md_batch_lds_bytes(6, 8, 3, 4) == 0
     assert lib.md_batch_lds_bytes(10, 8, 3, 4) == 10 * lib.md_batch_lds_bytes(1, 8, 3, 4)
+    # never less than one dx_k of 64 unknowns (kept in LDS during the stages)
+    assert lib.md_batch_lds_bytes(4, 0, 0, 1) == 8 * 2 * 4 * 64
+    assert lib.md_batch_lds_bytes(2, 1, 1, 1) == 8 * 2 * 2 * 64
     lib.md_device_dies.argtypes = [P, i, P]
     assert lib.md_device_dies(None, 4, None) == 3
     assert lib.md_device_dies(fake, 0, None) == 1
