@@ -48,9 +48,9 @@ TRAFFIC = {
                        "sha256": "e656748b5b420a2bb5d6457164b20b8f4524ae62440d00d9f88fd6ac86860dad",
                        "sources": ("batch.hip", "batch_kernel.hpp", "internal.hpp", "common.hpp",
                                    "md.hpp", "wg.hpp", "layout.hpp", "series.hpp")},
-    "k_qr": {"fetch_kib": 102.375, "fetch_scale": 262144 / 131088.4375, "write_kib": 67.0,
-             "write_scale": 262144 / 262147.375,
-             "sha256": "0fc92edd64bf7ae5ffed7f639bf2640b416b158e7ae0ee7308601bd39eef9514",
+    "k_qr": {"fetch_kib": 106.0625, "fetch_scale": 262144 / 131088.125, "write_kib": 67.0,
+             "write_scale": 262144 / 262144.625,
+             "sha256": "259af96bf92a7a3ffa11bfb26848b07da00fe4b5222290ffa1e719006752d7ab",
              "sources": ("qr.hip", "internal.hpp", "common.hpp", "md.hpp", "wg.hpp",
                          "layout.hpp", "series.hpp")},
 }
