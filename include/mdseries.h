@@ -147,6 +147,24 @@ int md_poly_eval_diff(int m, int d, const md_system *sys, const double *x, doubl
 int md_qr(int m, int N, int n, const double *A0, double *QR, double *vdiag, double *beta,
           int32_t *status, void *stream);
 
+/* md_qr with the trailing columns of each column step spread over
+ * md_qr_gang_size(m, N, n) workgroups that meet at a barrier in device
+ * memory after every step (the factorisation is the same, bit for bit;
+ * Section 4).  For one large system a workgroup is one CU's issue rate, so
+ * the spread shortens the factorisation (octo double, 64 x 64: the column
+ * updates of a step in one round instead of sixteen).  sync: one device
+ * int32 the call clears and uses (caller-owned; calls that share it must not
+ * overlap).  The workgroups must be resident together: with the GPU full of
+ * other work the barriers wait, and after a bounded wait they set
+ * MD_ST_GANG in status and the factors are not valid.  Errors as md_qr, and
+ * MD_ENULL for a null sync. */
+int md_qr_gang(int m, int N, int n, const double *A0, double *QR, double *vdiag, double *beta,
+               int32_t *sync, int32_t *status, void *stream);
+
+/* Workgroups md_qr_gang uses for an N x n factorisation (1: it runs as
+ * md_qr); 0 for invalid arguments. */
+int md_qr_gang_size(int m, int N, int n);
+
 /* Solution of the linearised system A(t) dx(t) = b(t), the block lower
  * triangular Toeplitz system of Section 4, by forward substitution over the
  * degrees: A_0 dx_k = b_k - A_1 dx_{k-1} - ... - A_k dx_0, k = 0..d, each

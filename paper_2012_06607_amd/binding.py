@@ -56,6 +56,8 @@ def lib() -> ctypes.CDLL:
         L.md_series_convolve.argtypes = [i32, i32, i64, P, P, P, P]
         L.md_poly_eval_diff.argtypes = [i32, i32, ctypes.POINTER(md_system), P, P, P, P, sz, P]
         L.md_qr.argtypes = [i32, i32, i32, P, P, P, P, P, P]
+        L.md_qr_gang.argtypes = [i32, i32, i32, P, P, P, P, P, P, P]
+        L.md_qr_gang_size.argtypes = [i32, i32, i32]
         L.md_series_solve.argtypes = [i32, i32, i32, i32, P, P, P, P, P, P, P, sz, P, P]
         L.md_newton_step.argtypes = [i32, i32, ctypes.POINTER(md_system), P, P, P, sz, P, P]
         L.md_newton_step_noalloc.argtypes = [i32, i32, ctypes.POINTER(md_system), P, P, P, P]
@@ -273,6 +275,29 @@ def md_qr(A0: torch.Tensor, status: torch.Tensor | None = None, stream=None, QR=
     _check(lib().md_qr(m, N, n, _ptr(A0), _ptr(QR), _ptr(vd), _ptr(beta), _ptr(status, torch.int32),
                        _stream(stream)), "md_qr")
     return QR, vd, beta, status
+
+
+def md_qr_gang(A0: torch.Tensor, status: torch.Tensor | None = None, stream=None, QR=None,
+               vdiag=None, beta=None, sync: torch.Tensor | None = None):
+    """md_qr with the column updates spread over md_qr_gang_size workgroups
+    (same bits) -> (QR, vdiag, beta, status)."""
+    m = _limbs(A0)
+    _, _, N, n = A0.shape
+    QR = torch.empty_like(A0) if QR is None else QR
+    vd = torch.empty((2, m, n), dtype=torch.float64, device=A0.device) if vdiag is None else vdiag
+    beta = torch.empty((m, n), dtype=torch.float64, device=A0.device) if beta is None else beta
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=A0.device)
+    if sync is None:
+        sync = torch.zeros(1, dtype=torch.int32, device=A0.device)
+    _check(lib().md_qr_gang(m, N, n, _ptr(A0), _ptr(QR), _ptr(vd), _ptr(beta),
+                            _ptr(sync, torch.int32), _ptr(status, torch.int32), _stream(stream)),
+           "md_qr_gang")
+    return QR, vd, beta, status
+
+
+def md_qr_gang_size(m: int, N: int, n: int) -> int:
+    return int(lib().md_qr_gang_size(m, N, n))
 
 
 def md_series_solve(QR, vdiag, beta, A, b, dx=None, ws=None, status=None, stream=None):

@@ -10,9 +10,12 @@ namespace mds {
 int eval_diff_enqueue(int m, int d, const md_system &sys, const double *x, double *f, double *A,
                       void *ws, size_t ws_bytes, hipStream_t s, double *mono = nullptr,
                       const int32_t *gate = nullptr);
+// ctr (optional, device int32): spread the trailing columns over several
+// workgroups that meet at barriers on *ctr (same bits)
 int qr_enqueue(int m, int N, int n, const double *A0, long A0_stride_planes, double *QR,
                double *vdiag, double *beta, int32_t *status, hipStream_t s,
-               const int32_t *gate = nullptr);
+               const int32_t *gate = nullptr, int32_t *ctr = nullptr);
+int qr_gang_size(int m, int N, int n);
 // invd = 1 / R_ii and W = R^{-1} (Q^H)_{0:n} (row-major n x N); N <= 256
 int pinv_enqueue(int m, int N, int n, const double *QR, const double *vdiag, const double *beta,
                  double *invd, double *W, int32_t *status, hipStream_t s,

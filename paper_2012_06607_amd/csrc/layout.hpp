@@ -66,7 +66,7 @@ struct NewtonLayout {
     o += SolveLayout(m, N, n, d).bytes;
     off_eval = o;
     o += EvalLayout(m, N, n, d, M, max_deg).bytes;
-    off_ctr = o;  // the term queue of a gang of workgroups (batched launch)
+    off_ctr = o;  // a gang's term queue (batched launch), the QR's barrier word (one path)
     o += 256;
     bytes = o;
   }

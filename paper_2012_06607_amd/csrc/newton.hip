@@ -156,7 +156,9 @@ int newton_step_impl(int m, int d, const md_system *sys, double *x, double *dx_n
   int rc = eval_diff_enqueue(m, d, *sys, x, f, A, w + lay.off_eval, lay.bytes - lay.off_eval, s,
                              nullptr, gate);
   if (rc) return rc;
-  rc = qr_enqueue(m, N, n, A, long(d + 1) * N * n, QR, vd, beta, status, s, gate);
+  // the QR's columns over several workgroups, meeting on the word at off_ctr
+  rc = qr_enqueue(m, N, n, A, long(d + 1) * N * n, QR, vd, beta, status, s, gate,
+                  reinterpret_cast<int32_t *>(w + lay.off_ctr));
   if (rc) return rc;
   rc = solve_enqueue(m, N, n, d, QR, vd, beta, A, f, true, dx, w + lay.off_solve,
                      lay.off_eval - lay.off_solve, status, s, gate);

@@ -74,6 +74,14 @@ def test_argument_errors_return_codes(lib):
     assert lib.md_series_convolve(2, 8, 0, fake, fake, fake, None) == 0           # nothing to do
     assert lib.md_series_convolve(2, 8, 0, None, None, None, None) == 0           # empty: no pointers needed
     assert lib.md_qr(2, 3, 4, fake, fake, fake, fake, None, None) == 2            # MD_ESHAPE (N < n)
+    lib.md_qr_gang.argtypes = [ctypes.c_int] * 3 + [P] * 7
+    assert lib.md_qr_gang(4, 8, 8, fake, fake, fake, fake, None, None, None) == 3  # no sync word
+    assert lib.md_qr_gang(4, 3, 4, fake, fake, fake, fake, fake, None, None) == 2  # N < n
+    lib.md_qr_gang_size.argtypes = [ctypes.c_int] * 3
+    assert lib.md_qr_gang_size(8, 64, 64) == 16      # 63 columns, 4 one-wave segments a workgroup
+    assert lib.md_qr_gang_size(4, 32, 32) == 2       # 31 columns, 16 segments a workgroup
+    assert lib.md_qr_gang_size(2, 1, 1) == 1
+    assert lib.md_qr_gang_size(6, 8, 8) == 0
     assert lib.md_elementwise(2, 99, 4, fake, fake, fake, None) == 1              # unknown op
     assert lib.md_norm2(2, 0, fake, fake, None) == 1                              # empty vector
     assert lib.md_newton_step(2, 8, None, fake, None, fake, 1 << 20, None, None) == 3

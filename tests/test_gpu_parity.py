@@ -262,6 +262,26 @@ def test_qr_tall_four_rows_per_lane(B, m):
     compare_qr((host(QR), host(vd), host(beta)), (QRw, vdw, bw), m, s[0] / s[-1])
 
 
+@pytest.mark.parametrize("m,N,n", ((8, 64, 64), (10, 64, 64), (4, 32, 32), (2, 70, 24),
+                                   (4, 140, 60), (5, 9, 9), (1, 1, 1), (3, 3, 2)))
+def test_qr_gang_same_bits_as_one_workgroup(B, m, N, n):
+    """md_qr_gang spreads each step's column updates over several
+    workgroups with device barriers; the factors are md_qr's bit for bit
+    (the oracle comparison of md_qr covers their accuracy), also on a
+    second call that reuses the synchronisation word."""
+    A0 = dev(I.unit_complex(I.rng(959, m, N, n), m, N, n))
+    QR, vd, beta, st = B.md_qr(A0)
+    sync = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for _ in range(2):
+        QRg, vdg, bg, stg = B.md_qr_gang(A0, sync=sync)
+        assert int(host(stg)[0]) == int(host(st)[0]) == 0
+        assert np.array_equal(host(QRg), host(QR))
+        assert np.array_equal(host(vdg), host(vd))
+        assert np.array_equal(host(bg), host(beta))
+    if n > 16:
+        assert B.md_qr_gang_size(m, N, n) > 1
+
+
 def test_qr_flags_singular_column(B):
     m = 2
     A0 = I.unit_complex(I.rng(957), m, 5, 5)
