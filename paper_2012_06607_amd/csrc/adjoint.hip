@@ -132,7 +132,8 @@ extern "C" int md_newton_adjoint(int m, int d, const md_system *sys, const doubl
   if (rc) return rc;
   rc = qr_enqueue(m, N, n, A, long(d + 1) * N * n, QR, vd, beta, status, s);
   if (rc) return rc;
-  rc = pinv_enqueue(m, N, n, QR, vd, beta, invd, W, status, s);
+  rc = pinv_enqueue(m, N, n, QR, vd, beta, invd, W,
+                    reinterpret_cast<double *>(w + nl.off_solve + sl.off_pw), status, s);
   if (rc) return rc;
   return dispatch_m(m, [&](auto Mc) {
     constexpr int Mm = decltype(Mc)::value;

@@ -16,9 +16,10 @@ int qr_enqueue(int m, int N, int n, const double *A0, long A0_stride_planes, dou
                double *vdiag, double *beta, int32_t *status, hipStream_t s,
                const int32_t *gate = nullptr, int32_t *ctr = nullptr);
 int qr_gang_size(int m, int N, int n);
-// invd = 1 / R_ii and W = R^{-1} (Q^H)_{0:n} (row-major n x N); N <= 256
+// invd = 1 / R_ii and W = R^{-1} (Q^H)_{0:n} (row-major n x N); N <= 256;
+// scratch: SolveLayout's off_pw region (2 m (4 n^2 + 2 n N) doubles)
 int pinv_enqueue(int m, int N, int n, const double *QR, const double *vdiag, const double *beta,
-                 double *invd, double *W, int32_t *status, hipStream_t s,
+                 double *invd, double *W, double *scratch, int32_t *status, hipStream_t s,
                  const int32_t *gate = nullptr);
 int solve_enqueue(int m, int N, int n, int d, const double *QR, const double *vdiag,
                   const double *beta, const double *A, const double *b, bool negate_b,

@@ -35,12 +35,15 @@ struct EvalLayout {
 
 // Staggered solve: the right hand sides r (d+1, N), the n x N matrix
 // W = R^{-1} (Q^H)_{0:n}, then 1/R_ii (n).
+// Staggered solve: the right-hand sides r (d+1 x N), W (n x N) and 1/R_ii
+// (n), then the scratch of the one-path W formation (pinv_scratch_doubles).
 struct SolveLayout {
-  size_t off_r, off_G, bytes;
+  size_t off_r, off_G, off_pw, bytes;
   __host__ __device__ SolveLayout(int m, int N, int n, int d) {
     off_r = 0;
     off_G = align256(sizeof(double) * 2 * m * size_t(d + 1) * N);
-    bytes = off_G + align256(sizeof(double) * 2 * m * (size_t(n) * N + n));
+    off_pw = off_G + align256(sizeof(double) * 2 * m * (size_t(n) * N + n));
+    bytes = off_pw + align256(sizeof(double) * 2 * m * (4 * size_t(n) * n + 2 * size_t(n) * N));
   }
 };
 

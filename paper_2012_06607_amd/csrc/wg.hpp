@@ -339,110 +339,8 @@ __device__ __forceinline__ void inv_diag_range(int t, int nt, int N, int n, cons
   }
 }
 
-// Column c of W = R^{-1} (Q^H)_{0:n} by one segment (lanes own rows
-// lis, lis+seg, ...): identity column, n reflectors in order, then the back
-// substitution with the row owner multiplying by 1/R_ii and broadcasting.
-// W: row-major n x N.  `live` false: the segment only joins the shuffles.
-template <int M, int RPL, bool PF = false>
-__device__ __forceinline__ void pinv_column(bool live, int c, int N, int n, int seg,
-                            const double *__restrict__ QR, const double *__restrict__ vdiag,
-                            const double *__restrict__ beta, const double *__restrict__ invd,
-                            double *__restrict__ W) {
-  const long E = long(N) * n;
-  const long EW = long(n) * N;
-  const int lane = lane_id();
-  const int lis = lane & (seg - 1);
-  mdc<M> g[RPL];
-#pragma unroll
-  for (int r = 0; r < RPL; ++r) {
-    g[r] = c_zero<M>();
-    if (live && lis + r * seg == c) g[r].re = md_from<M>(1.0);
-  }
-  // reflector j's head, beta and this lane's rows of its tail; with PF the
-  // next reflector's are loaded while this one is applied
-  auto load_v = [&](int j, mdc<M> &v0, mdr<M> &bet, mdc<M> (&vi)[RPL]) {
-    v0 = cload<M>(vdiag, n, j);
-    bet = rload<M>(beta, n, j);
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-      const int i = lis + r * seg;
-      vi[r] = c_zero<M>();
-      if (live && i > j && i < N) vi[r] = cload<M>(QR, E, long(i) * n + j);
-    }
-  };
-  // with four or more rows per lane and no prefetch the reflector's rows are
-  // not held in registers: each is read where it is used (twice, through L1)
-  constexpr bool HOLD = RPL < 4 || PF;
-  mdc<M> v0n, vin[HOLD ? RPL : 1];
-  mdr<M> betn;
-  if constexpr (PF) {
-    if (n > 0) load_v(0, v0n, betn, vin);
-  }
-  for (int j = 0; j < n; ++j) {
-    mdc<M> v0, vi[HOLD ? RPL : 1];
-    mdr<M> bet;
-    if constexpr (PF) {
-      v0 = v0n;
-      bet = betn;
-#pragma unroll
-      for (int r = 0; r < RPL; ++r) vi[r] = vin[r];
-      if (j + 1 < n) load_v(j + 1, v0n, betn, vin);
-    } else if constexpr (HOLD) {
-      load_v(j, v0, bet, vi);
-    } else {
-      v0 = cload<M>(vdiag, n, j);
-      bet = rload<M>(beta, n, j);
-    }
-    auto vrow = [&](int r, int i) __attribute__((always_inline)) {
-      if constexpr (HOLD) return i == j ? v0 : vi[r];
-      else return i == j ? v0 : cload<M>(QR, E, long(i) * n + j);
-    };
-    mdc<M> w = c_zero<M>();
-    bool first = true;
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-      const int i = lis + r * seg;
-      if (live && i >= j && i < N) {
-        const mdc<M> t = c_mul<M>(c_conj<M>(vrow(r, i)), g[r]);
-        w = first ? t : c_add<M>(w, t);
-        first = false;
-      }
-    }
-    if constexpr (!HOLD) asm volatile("" ::: "memory");  // read the rows again below
-    w = seg_reduce_c<M>(w, seg);
-    w = shfl_c<M>(w, lane & ~(seg - 1));
-    const mdc<M> bw = c_mulr<M>(w, bet);
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-      const int i = lis + r * seg;
-      if (live && i >= j && i < N) g[r] = c_sub<M>(g[r], c_mul<M>(bw, vrow(r, i)));
-    }
-  }
-  for (int i = n - 1; i >= 0; --i) {
-    const int owner = i & (seg - 1), ro = i / seg;
-    mdc<M> xi = c_zero<M>();
-#pragma unroll
-    for (int r = 0; r < RPL; ++r)
-      if (live && r == ro && lis == owner) xi = c_mul<M>(g[r], cload<M>(invd, n, i));
-    xi = shfl_c<M>(xi, (lane & ~(seg - 1)) + owner);
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-      const int l = lis + r * seg;
-      if (!live) continue;
-      if (l == i) g[r] = xi;
-      else if (l < i) g[r] = c_sub<M>(g[r], c_mul<M>(cload<M>(QR, E, long(l) * n + i), xi));
-    }
-  }
-  if (live) {
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-      const int i = lis + r * seg;
-      if (i < n) cstore<M>(W, EW, long(i) * N + c, g[r]);
-    }
-  }
-}
-
-// The same W in two passes with less work.  Row r of (Q^H)_{0:n} is the
+// W = R^{-1} (Q^H)_{0:n} in two passes (the batched kernel's form).  Row r
+// of (Q^H)_{0:n} is the
 // conjugate of column r of Q, and Q e_r = H_0 H_1 ... H_r e_r because H_j
 // (zero above row j) leaves e_r alone for j > r: r + 1 reflectors instead of
 // n.  q_row forms that row (one segment, lanes own entries lis, lis+seg,
@@ -564,7 +462,7 @@ __device__ __forceinline__ void backsub_column(bool live, int c, int N, int n, i
 }
 
 // x = R^{-1} (Q^H b)_{0:n} for one right-hand side b (N entries) by one
-// segment: b's rows go to the lanes as in pinv_column, the n reflectors are
+// segment (lanes own rows lis, lis+seg, ...), the n reflectors are
 // applied in order, then the back substitution with the row owner
 // multiplying by 1/R_ii and broadcasting.  x: n entries (plane stride n).
 // `live` false: the segment only joins the shuffles.
