@@ -206,6 +206,57 @@ __device__ __forceinline__ mdr<M> md_sub(const mdr<M> &a, const mdr<M> &b) {
   return md_add<M>(a, md_neg<M>(b));
 }
 
+// The level sums of the product a b (M >= 3) before renormalisation: c_k
+// collects level k's products and the errors carried from level k-1, and
+// c_0 + ... + c_{M-1} is the product md_mul renormalises.
+template <int M>
+__device__ __forceinline__ void mul_levels(const mdr<M> &a, const mdr<M> &b, double (&c)[M]) {
+  constexpr int CMAX = mul_level_terms(M - 1);
+  double carry[CMAX];
+  double lo[M];
+  static_for<0, M>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    constexpr int ncar = (k == 0) ? 0 : mul_level_terms(k - 1) - 1;
+    constexpr int nt = (k + 1) + k + ncar;
+    if constexpr (k == M - 1) {
+      // the last level: plain products and a plain sum
+      double s = a.v[0] * b.v[k];
+      static_for<1, k + 1>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        s = s + a.v[i] * b.v[k - i];
+      });
+      static_for<0, k>([&](auto ic) { s = s + lo[decltype(ic)::value]; });
+      static_for<0, ncar>([&](auto ic) { s = s + carry[decltype(ic)::value]; });
+      c[k] = s;
+    } else {
+      double terms[CMAX];
+      double newlo[M];
+      static_for<0, k + 1>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        two_prod(a.v[i], b.v[k - i], terms[i], newlo[i]);
+      });
+      static_for<0, k>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        terms[k + 1 + i] = lo[i];
+      });
+      static_for<0, ncar>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        terms[2 * k + 1 + i] = carry[i];
+      });
+      double s = terms[0];
+      static_for<1, nt>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        double ns, e;
+        two_sum(s, terms[i], ns, e);
+        s = ns;
+        carry[i - 1] = e;
+      });
+      c[k] = s;
+      static_for<0, k + 1>([&](auto ic) { lo[decltype(ic)::value] = newlo[decltype(ic)::value]; });
+    }
+  });
+}
+
 template <int M>
 __device__ __forceinline__ mdr<M> md_mul(const mdr<M> &a, const mdr<M> &b) {
   if constexpr (M == 1) {
@@ -225,53 +276,55 @@ __device__ __forceinline__ mdr<M> md_mul(const mdr<M> &a, const mdr<M> &b) {
     z.v[1] = e;
     return z;
   } else {
-    constexpr int CMAX = mul_level_terms(M - 1);
-    double carry[CMAX];
-    double lo[M];
     double c[M];
-    static_for<0, M>([&](auto kc) {
-      constexpr int k = decltype(kc)::value;
-      constexpr int ncar = (k == 0) ? 0 : mul_level_terms(k - 1) - 1;
-      constexpr int nt = (k + 1) + k + ncar;
-      if constexpr (k == M - 1) {
-        // the last level: plain products and a plain sum
-        double s = a.v[0] * b.v[k];
-        static_for<1, k + 1>([&](auto ic) {
-          constexpr int i = decltype(ic)::value;
-          s = s + a.v[i] * b.v[k - i];
-        });
-        static_for<0, k>([&](auto ic) { s = s + lo[decltype(ic)::value]; });
-        static_for<0, ncar>([&](auto ic) { s = s + carry[decltype(ic)::value]; });
-        c[k] = s;
-      } else {
-        double terms[CMAX];
-        double newlo[M];
-        static_for<0, k + 1>([&](auto ic) {
-          constexpr int i = decltype(ic)::value;
-          two_prod(a.v[i], b.v[k - i], terms[i], newlo[i]);
-        });
-        static_for<0, k>([&](auto ic) {
-          constexpr int i = decltype(ic)::value;
-          terms[k + 1 + i] = lo[i];
-        });
-        static_for<0, ncar>([&](auto ic) {
-          constexpr int i = decltype(ic)::value;
-          terms[2 * k + 1 + i] = carry[i];
-        });
-        double s = terms[0];
-        static_for<1, nt>([&](auto ic) {
-          constexpr int i = decltype(ic)::value;
-          double ns, e;
-          two_sum(s, terms[i], ns, e);
-          s = ns;
-          carry[i - 1] = e;
-        });
-        c[k] = s;
-        static_for<0, k + 1>([&](auto ic) { lo[decltype(ic)::value] = newlo[decltype(ic)::value]; });
-      }
-    });
+    mul_levels<M>(a, b, c);
     return renorm<M, M>(c);
   }
+}
+
+// x + y + z for three sets of M level sums (limbs, or mul_levels output),
+// by md_add's level cascade with three inputs a level: level i sums x_i,
+// y_i, z_i and the errors carried from level i-1 by two-sums (its own
+// errors going to level i+1), the last level in plain arithmetic, then one
+// renormalisation.  With products as mul_levels gives them this is a fused
+// multiply-add: one renormalisation instead of three.
+template <int M>
+__device__ __forceinline__ mdr<M> sum3_levels(const double (&x)[M], const double (&y)[M],
+                                              const double (&z)[M]) {
+  double carry[2 * M + 2];
+  double c[M + 1];
+  static_for<0, M + 1>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    constexpr int nin = 2 * i;  // carries from level i-1
+    if constexpr (i == M) {
+      // a level below the last limb: the carries in plain arithmetic
+      double s = carry[0];
+      static_for<1, nin>([&](auto qc) { s = s + carry[decltype(qc)::value]; });
+      c[i] = s;
+    } else {
+      double s = x[i];
+      double nc[2 * M + 2];
+      {
+        double ns, e;
+        two_sum(s, y[i], ns, e);
+        s = ns;
+        nc[0] = e;
+        two_sum(s, z[i], ns, e);
+        s = ns;
+        nc[1] = e;
+      }
+      static_for<0, nin>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        double ns, e;
+        two_sum(s, carry[q], ns, e);
+        s = ns;
+        nc[q + 2] = e;
+      });
+      c[i] = s;
+      static_for<0, nin + 2>([&](auto qc) { carry[decltype(qc)::value] = nc[decltype(qc)::value]; });
+    }
+  });
+  return renorm<M, M + 1>(c);
 }
 
 // multiple double times hardware double
@@ -455,6 +508,30 @@ __device__ __forceinline__ mdc<M> c_mul(const mdc<M> &a, const mdc<M> &b) {
   z.re = md_add<M>(p1, md_neg<M>(p2));
   z.im = md_add<M>(p3, p4);
   return z;
+}
+
+// s + a b for complex multiple doubles: up to double double c_add(s, c_mul(a, b));
+// from three limbs on fused: the four real products as level sums, then
+// s.re + (a.re b.re) + (-(a.im b.im)) and s.im + (a.re b.im) + (a.im b.re),
+// each with one renormalisation (the same value to the last limb's
+// rounding, with two renormalisations fewer per part).
+template <int M>
+__device__ __forceinline__ mdc<M> c_fmadd(const mdc<M> &s, const mdc<M> &a, const mdc<M> &b) {
+  if constexpr (M <= 2) {
+    return c_add<M>(s, c_mul<M>(a, b));
+  } else {
+    double p1[M], p2[M], p3[M], p4[M];
+    mul_levels<M>(a.re, b.re, p1);
+    mul_levels<M>(a.im, b.im, p2);
+    mul_levels<M>(a.re, b.im, p3);
+    mul_levels<M>(a.im, b.re, p4);
+#pragma unroll
+    for (int i = 0; i < M; ++i) p2[i] = -p2[i];
+    mdc<M> z;
+    z.re = sum3_levels<M>(s.re.v, p1, p2);
+    z.im = sum3_levels<M>(s.im.v, p3, p4);
+    return z;
+  }
 }
 
 template <int M>

@@ -608,8 +608,8 @@ __device__ __forceinline__ void stage_update_row_lds(bool live, long row, int k,
   bool first = true;
   if (live)
     for (int l = lis; l < n; l += seg) {
-      const mdc<M> t = c_mul<M>(cload<M>(A, EA, (long(j) * N + i) * n + l), cload<M>(dxl, n, l));
-      s = first ? t : c_add<M>(s, t);
+      const mdc<M> a = cload<M>(A, EA, (long(j) * N + i) * n + l), x = cload<M>(dxl, n, l);
+      s = first ? c_mul<M>(a, x) : c_fmadd<M>(s, a, x);
       first = false;
     }
   s = seg_reduce_c<M>(s, seg);
@@ -709,8 +709,16 @@ __device__ __forceinline__ mdc<M> conv_part(const mdc<M> *X, int dx, const mdc<M
   mdc<M> acc = c_zero<M>();
   bool first = true;
   for (int i = sub; i <= top; i += r) {
-    const mdc<M> t = c_mul<M>(X[i], Y[k - i]);
-    acc = first ? t : c_add<M>(acc, t);
+    if (first) {
+      acc = c_mul<M>(X[i], Y[k - i]);
+    } else if constexpr (M <= 4) {
+      acc = c_fmadd<M>(acc, X[i], Y[k - i]);
+    } else {
+      // five limbs and more: the two operations (the fused form makes the
+      // shared series-product routine of those kernels too long for its
+      // short branches)
+      acc = c_add<M>(acc, c_mul<M>(X[i], Y[k - i]));
+    }
     first = false;
   }
   return acc;
