@@ -734,9 +734,11 @@ template <int M>
 __device__ __forceinline__ void conv_block(int bl, int nb, const mdc<M> *X, int dx, const mdc<M> *Y,
                                            mdc<M> *Z, int d, int r, double *ws, long Ews,
                                            long wbase, int mult) {
-  if (dx < r) {
-    // a short X (a coefficient series): one coefficient per lane, its few
-    // products added in sequence
+  if (dx < r && dx < d) {
+    // a short X (a coefficient series, deg X < d): one coefficient per
+    // lane, its few products added in sequence.  (A full product of a short
+    // series, d < r, still goes through the lane groups: one coefficient
+    // per lane would make its last lane add d + 1 products in sequence.)
     for (int k = bl; k <= d; k += nb) {
       mdc<M> z = conv_part<M>(X, dx, Y, k, 0, 1);
       if (mult > 1) {
