@@ -93,6 +93,8 @@ def parse():
     ap.add_argument("--no-high-precision", action="store_true",
                     help="skip the octo / deca double step at 64 unknowns, d = 32")
     ap.add_argument("--hp-reps", type=int, default=3)
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the least-squares, protocol, division and Pade measurements")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint measurement (32 unknowns, d = 16, quad double)")
     ap.add_argument("--adj-reps", type=int, default=20)
@@ -455,6 +457,91 @@ def gang_step(B, OC, m: int, reps: int) -> dict:
             "status": int(batch.status.max().item())}
 
 
+def next_rows(args, B, OC) -> dict:
+    """The rows beyond the Newton step, each on a stated synthetic workload:
+    least squares (one quad-double step of a consistent 39 x 32 system, the
+    square system of 32 equations plus 7 sums of pairs of them, d = 16);
+    Section 6's protocol in the persistent launch (1024 paths shaped as the
+    headline batch's, degrees 8, 16, 24, 32 with at most 8, 8, 12, 16 steps,
+    stop at |dx_d| <= 1e-32, longest first by operation count, one queue);
+    series division (64 octo-double series of 33
+    coefficients) and [16/16] Pade approximants (64 quad-double series)."""
+    import numpy as np
+    import torch
+    from paper_2012_06607_amd import inputs as I
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {}
+    # least squares: N = n + 7
+    m, n, d = 4, 32, 16
+    sq, x0 = I.newton_system((6, 0), n, m)
+    sysm = I.augmented_system((6, 1), sq)
+    sd = B.DeviceSystem(sysm)
+    x = torch.as_tensor(I.series_start(x0, d), device="cuda")
+    ws = B.workspace(B.MD_FN_NEWTON, m, sysm.N, n, d, sysm.M, sysm.max_deg)
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    nrm = torch.zeros((m, 2), dtype=torch.float64, device="cuda")
+    ms = timed(lambda: B.md_newton_step(sd, x, nrm, ws, st, stream), 5)
+    ops = OC.newton_step(sysm, d, m).table_ops(m)
+    out["least_squares"] = {"workload": f"qd, N = {sysm.N} equations (32 + 7 sums of pairs), "
+                                        f"n = {n}, d = {d}: one md_newton_step",
+                            "ms_per_step": round(ms, 4),
+                            "pct_fp64_vector_peak": round(100.0 * ops / (ms * 1e-3)
+                                                          / OC.FP64_VECTOR_PEAK, 4)}
+    # Section 6's protocol, batched
+    specs = I.batch_specs((7, 0), 1024, d_range=(32, 32))
+    paths = []
+    for sp in specs:
+        sy, xs = I.newton_system((7, sp.path), sp.n, sp.m)
+        paths.append((sy, I.series_start(xs, 32)))
+    batch = B.BatchedPaths(paths, protocol=True)
+    B.md_newton_batch_protocol(batch, stream=stream)
+    torch.cuda.synchronize()
+    batch.restore()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    its, _ = B.md_newton_batch_protocol(batch, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    pms = e0.elapsed_time(e1)
+    it = its.cpu().numpy()
+    stt = batch.status.cpu().numpy()
+    steps = int(it.sum())
+    out["protocol"] = {"workload": "1024 paths (n in 8..64, half dd / half qd, 8 monomials of "
+                                   "degree <= 3 + constant + t-term per equation), degrees 8, 16, "
+                                   "24, 32 with at most 8, 8, 12, 16 steps, stop at "
+                                   "|dx_d| <= 1e-32, one persistent launch",
+                       "ms_per_launch": round(pms, 3), "newton_steps": steps,
+                       "newton_steps_per_s": round(steps / (pms * 1e-3), 1),
+                       "steps_per_degree": [int(v) for v in it.sum(axis=0)],
+                       "paths_flagged_diverged": int(((stt & B.MD_ST_DIVERGED) != 0).sum()),
+                       "other_status_bits": int((stt & ~B.MD_ST_DIVERGED).max())}
+    # series division and Pade approximants
+    g = I.rng(8, 0)
+    xd = torch.as_tensor(I.unit_complex(g, 8, 64, 33), device="cuda")
+    yd = torch.as_tensor(I.unit_complex(g, 8, 64, 33), device="cuda")
+    yd[:, :, :, 0] *= 4.0   # y_0 away from zero
+    out["series_division"] = {"workload": "64 od series of 33 coefficients",
+                              "ms": round(timed(lambda: B.md_series_divide(xd, yd, stream=stream),
+                                                10), 4)}
+    cp = torch.as_tensor(I.unit_complex(g, 4, 64, 33), device="cuda")
+    out["pade"] = {"workload": "[16/16] approximants of 64 qd series of 33 coefficients",
+                   "ms": round(timed(lambda: B.md_series_pade(cp, 16, 16, stream=stream), 10), 4)}
+    return out
+
+
 def adjoint_measure(args, B, OC) -> dict:
     """Quad double series Newton on a 32-unknown system (8 monomials of degree
     <= 3, a constant and a t-term per equation: 320 coefficients), d = 16,
@@ -668,6 +755,8 @@ def main():
         line["adjoint"] = adjoint_measure(args, B, OC)
     if not args.no_high_precision:
         line["high_precision"] = high_precision(args, B, OC)
+    if not args.no_next:
+        line["next_rows"] = next_rows(args, B, OC)
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
