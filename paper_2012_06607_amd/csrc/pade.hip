@@ -31,6 +31,52 @@ __global__ void __launch_bounds__(64) k_series_divide(int d, long count,
   }
 }
 
+// The same quotients with the products of each coefficient side by side:
+// one wave per series, its lanes form y_i z_{k-i} for i = 1..k at once into
+// LDS, then lane 0 adds them in increasing i, subtracts from x_k and
+// divides by y_0 (the sequential definition's bits; the chain per
+// coefficient is one product instead of k).  LDS per wave: the products
+// (d) and the quotients so far (d+1), planes of complex md numbers.
+template <int M>
+__global__ void __launch_bounds__(256) k_series_divide_wave(int d, long count,
+                                                            const double *__restrict__ x,
+                                                            const double *__restrict__ y,
+                                                            double *__restrict__ z,
+                                                            int32_t *status) {
+  extern __shared__ double lds[];
+  const int wave = threadIdx.x / WAVE, lane = lane_id();
+  const long c = long(blockIdx.x) * (blockDim.x / WAVE) + wave;
+  const int L = d + 1;
+  double *pr = lds + size_t(wave) * 2 * M * (2 * L);  // products 1..d at 0..d-1
+  double *zs = pr + size_t(2) * M * L;                 // z_0..z_d
+  if (c >= count) return;  // whole waves: no barrier below spans waves
+  const long E = count * L, b = c * L;
+  const mdc<M> y0 = cload<M>(y, E, b);
+  if (lane == 0 && y0.re.v[0] == 0.0 && y0.im.v[0] == 0.0 && status)
+    atomicOr(status, MD_ST_SINGULAR);
+  for (int k = 0; k <= d; ++k) {
+    for (int i = 1 + lane; i <= k; i += WAVE)
+      cstore<M>(pr, L, i - 1, c_mul<M>(cload<M>(y, E, b + i), cload<M>(zs, L, k - i)));
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane == 0) {
+      mdc<M> r = cload<M>(x, E, b + k);
+      if (k > 0) {
+        mdc<M> sm = cload<M>(pr, L, 0);
+        for (int i = 2; i <= k; ++i) sm = c_add<M>(sm, cload<M>(pr, L, i - 1));
+        r = c_sub<M>(r, sm);
+      }
+      const mdc<M> zk = c_div<M>(r, y0);
+      cstore<M>(z, E, b + k, zk);
+      cstore<M>(zs, L, k, zk);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
 // [L/Md] Pade approximant of one series per workgroup: the Toeplitz system
 // sum_j c_{L+i-j} q_j = -c_{L+i} (i, j = 1..Md) by Householder QR (the QR
 // and reflector solve of the Newton step), q_0 = 1, then
@@ -103,10 +149,20 @@ extern "C" int md_series_divide(int m, int d, int64_t count, const double *x, co
   if (!x || !y || !z) return fail(MD_ENULL, "md_series_divide: null pointer");
   return dispatch_m(m, [&](auto Mc) {
     constexpr int Mm = decltype(Mc)::value;
-    const long blocks = (long(count) + 63) / 64;
-    if (blocks > 0x7fffffffL) return fail(MD_ESHAPE, "md_series_divide: count too large");
-    k_series_divide<Mm><<<dim3(unsigned(blocks)), dim3(64), 0, (hipStream_t)stream>>>(
-        d, long(count), x, y, z, status);
+    // four series a workgroup (a wave each) while their products and
+    // quotients fit in LDS, else one lane per series
+    const size_t lds = sizeof(double) * 2 * Mm * 2 * size_t(d + 1) * 4;
+    if (lds <= lds_limit()) {
+      const long blocks = (long(count) + 3) / 4;
+      if (blocks > 0x7fffffffL) return fail(MD_ESHAPE, "md_series_divide: count too large");
+      k_series_divide_wave<Mm><<<dim3(unsigned(blocks)), dim3(256), lds, (hipStream_t)stream>>>(
+          d, long(count), x, y, z, status);
+    } else {
+      const long blocks = (long(count) + 63) / 64;
+      if (blocks > 0x7fffffffL) return fail(MD_ESHAPE, "md_series_divide: count too large");
+      k_series_divide<Mm><<<dim3(unsigned(blocks)), dim3(64), 0, (hipStream_t)stream>>>(
+          d, long(count), x, y, z, status);
+    }
     return check_launch("md_series_divide");
   });
 }

@@ -49,6 +49,20 @@ def test_divide_bit_exact(B, m, count, d):
     assert np.array_equal(host(z), want)
 
 
+@pytest.mark.parametrize("m,count,d", ((2, 5, 100), (4, 2, 70), (10, 1, 600)))
+def test_divide_long_series(B, m, count, d):
+    # more products per coefficient than lanes (d > 64), and deca double at
+    # d = 600, whose products do not fit in LDS (one lane per series)
+    g = I.rng(1512, m, count, d)
+    x = I.unit_complex(g, m, count, d + 1)
+    y = I.unit_complex(g, m, count, d + 1)
+    y[:, :, :, 0] *= 4.0
+    want, stw = oracle.series_divide(x, y)
+    z, st = B.md_series_divide(dev(x), dev(y))
+    assert int(host(st)[0]) == stw == 0
+    assert np.array_equal(host(z), want)
+
+
 def test_divide_flags_zero_constant(B):
     m = 2
     x = I.unit_complex(I.rng(1511), m, 4, 5)
