@@ -130,7 +130,8 @@ extern "C" int md_newton_adjoint(int m, int d, const md_system *sys, const doubl
   double *mono = store ? reinterpret_cast<double *>(w + lay.off_mono) : nullptr;
   int rc = eval_diff_enqueue(m, d, *sys, x, f, A, w + nl.off_eval, nl.bytes - nl.off_eval, s, mono);
   if (rc) return rc;
-  rc = qr_enqueue(m, N, n, A, long(d + 1) * N * n, QR, vd, beta, status, s);
+  rc = qr_enqueue(m, N, n, A, long(d + 1) * N * n, QR, vd, beta, status, s, nullptr,
+                  reinterpret_cast<int32_t *>(w + nl.off_ctr));
   if (rc) return rc;
   rc = pinv_enqueue(m, N, n, QR, vd, beta, invd, W,
                     reinterpret_cast<double *>(w + nl.off_solve + sl.off_pw), status, s);

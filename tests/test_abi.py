@@ -80,6 +80,7 @@ def test_argument_errors_return_codes(lib):
     lib.md_qr_gang_size.argtypes = [ctypes.c_int] * 3
     assert lib.md_qr_gang_size(8, 64, 64) == 16      # 63 columns, 4 one-wave segments a workgroup
     assert lib.md_qr_gang_size(4, 32, 32) == 2       # 31 columns, 16 segments a workgroup
+    assert lib.md_qr_gang_size(4, 140, 60) == 8      # 59 columns, 8 four-row segments
     assert lib.md_qr_gang_size(2, 1, 1) == 1
     assert lib.md_qr_gang_size(6, 8, 8) == 0
     assert lib.md_elementwise(2, 99, 4, fake, fake, fake, None) == 1              # unknown op

@@ -278,8 +278,8 @@ def test_qr_gang_same_bits_as_one_workgroup(B, m, N, n):
         assert np.array_equal(host(QRg), host(QR))
         assert np.array_equal(host(vdg), host(vd))
         assert np.array_equal(host(bg), host(beta))
-    if n > 16:
-        assert B.md_qr_gang_size(m, N, n) > 1
+    if m >= 5 and n > 16:
+        assert B.md_qr_gang_size(m, N, n) > 1    # 256-thread workgroups: spread
 
 
 def test_qr_flags_singular_column(B):
