@@ -87,6 +87,13 @@ struct QrShared {
   mdr<M> beta[2];
 };
 
+template <int M>
+__device__ __forceinline__ void qr_reflector_scalars(const mdr<M> &s, const mdc<M> &alpha, int j,
+                                                     int n, bool keep, QrShared<M> &sh,
+                                                     double *__restrict__ QR, long E,
+                                                     double *__restrict__ vdiag,
+                                                     double *__restrict__ beta, int &st);
+
 // Reflector j from the column values the wave's first segment holds (rows
 // lis + r*seg): the segment tree of |a_i|^2 over i >= j, alpha from the lane
 // that holds row j; lane 0 of the wave stores the scalars when `keep` (all
@@ -123,13 +130,23 @@ __device__ __forceinline__ void qr_reflector(const mdc<M> (&col)[RPL], int j, in
     }
   }
   s = seg_reduce_r<M>(s, seg);
-  // The wave's first segment holds the column: its sums and alpha go to every
-  // lane, and the scalars are a short chain of md operations with the
-  // independent ones side by side on lanes 0..3 (lane 0 keeps the results):
-  // 1/sqrt and the product with it for sigma^2 (lane 0) and |alpha|^2
-  // (lane 1), then phi = alpha/|alpha| (re, im on lanes 0, 1), then v_0 =
-  // phi (|alpha| + sigma) and R_jj = -phi sigma (lanes 0..3).
   alpha = shfl_c<M>(alpha, j & (seg - 1));
+  qr_reflector_scalars<M>(s, alpha, j, n, keep, sh, QR, E, vdiag, beta, st);
+}
+
+// The scalars of reflector j from sigma^2 (on lane 0) and alpha (on every
+// lane), by one wave: a short chain of md operations with the independent
+// ones side by side on lanes 0..3 (lane 0 keeps the results): 1/sqrt and
+// the product with it for sigma^2 (lane 0) and |alpha|^2 (lane 1), then
+// phi = alpha/|alpha| (re, im on lanes 0, 1), then v_0 = phi (|alpha| +
+// sigma) and R_jj = -phi sigma (lanes 0..3).
+template <int M>
+__device__ __forceinline__ void qr_reflector_scalars(const mdr<M> &s, const mdc<M> &alpha, int j,
+                                                     int n, bool keep, QrShared<M> &sh,
+                                                     double *__restrict__ QR, long E,
+                                                     double *__restrict__ vdiag,
+                                                     double *__restrict__ beta, int &st) {
+  const int lane = lane_id();
   const int base = 0, sub = lane;
   const mdr<M> s2 = shfl_r<M>(s, base);
   const mdr<M> a2 = c_abs2<M>(alpha);

@@ -78,9 +78,14 @@ def test_argument_errors_return_codes(lib):
     assert lib.md_qr_gang(4, 8, 8, fake, fake, fake, fake, None, None, None) == 3  # no sync word
     assert lib.md_qr_gang(4, 3, 4, fake, fake, fake, fake, fake, None, None) == 2  # N < n
     lib.md_qr_gang_size.argtypes = [ctypes.c_int] * 3
-    assert lib.md_qr_gang_size(8, 64, 64) == 16      # 63 columns, 4 one-wave segments a workgroup
-    assert lib.md_qr_gang_size(4, 32, 32) == 2       # 31 columns, 16 segments a workgroup
-    assert lib.md_qr_gang_size(4, 140, 60) == 8      # 59 columns, 8 four-row segments
+    # from three limbs on, N <= 64: workgroup 0 takes the look-ahead column
+    # on four waves, the others the n - 2 columns after it
+    assert lib.md_qr_gang_size(8, 64, 64) == 17      # 1 + 62 columns / 4 one-wave segments
+    assert lib.md_qr_gang_size(4, 32, 32) == 3       # 1 + 30 columns / 16 segments
+    assert lib.md_qr_gang_size(3, 5, 3) == 2         # the smallest such column (8-lane segments)
+    assert lib.md_qr_gang_size(4, 4, 4) == 1         # N < 5: one workgroup
+    assert lib.md_qr_gang_size(2, 32, 32) == 1       # double double: 31 columns, 32 segments
+    assert lib.md_qr_gang_size(4, 140, 60) == 8      # N > 64: 59 columns, 8 four-row segments
     assert lib.md_qr_gang_size(2, 1, 1) == 1
     assert lib.md_qr_gang_size(6, 8, 8) == 0
     assert lib.md_elementwise(2, 99, 4, fake, fake, fake, None) == 1              # unknown op

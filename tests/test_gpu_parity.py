@@ -263,10 +263,13 @@ def test_qr_tall_four_rows_per_lane(B, m):
 
 
 @pytest.mark.parametrize("m,N,n", ((8, 64, 64), (10, 64, 64), (4, 32, 32), (2, 70, 24),
-                                   (4, 140, 60), (5, 9, 9), (1, 1, 1), (3, 3, 2)))
+                                   (4, 140, 60), (5, 9, 9), (1, 1, 1), (3, 3, 2), (3, 5, 3),
+                                   (4, 17, 12), (5, 33, 20), (8, 40, 33), (4, 64, 64)))
 def test_qr_gang_same_bits_as_one_workgroup(B, m, N, n):
     """md_qr_gang spreads each step's column updates over several
-    workgroups with device barriers; the factors are md_qr's bit for bit
+    workgroups with device barriers (from three limbs on and 5 <= N <= 64
+    with the look-ahead column on four waves of one workgroup, its complex
+    products one real product a lane); the factors are md_qr's bit for bit
     (the oracle comparison of md_qr covers their accuracy), also on a
     second call that reuses the synchronisation word."""
     A0 = dev(I.unit_complex(I.rng(959, m, N, n), m, N, n))
@@ -278,8 +281,8 @@ def test_qr_gang_same_bits_as_one_workgroup(B, m, N, n):
         assert np.array_equal(host(QRg), host(QR))
         assert np.array_equal(host(vdg), host(vd))
         assert np.array_equal(host(bg), host(beta))
-    if m >= 5 and n > 16:
-        assert B.md_qr_gang_size(m, N, n) > 1    # 256-thread workgroups: spread
+    if m >= 3 and 5 <= N <= 64 and n >= 3:
+        assert B.md_qr_gang_size(m, N, n) > 1    # the four-wave look-ahead form
 
 
 def test_qr_flags_singular_column(B):
