@@ -10,8 +10,8 @@
 // N columns of the identity.  After dx_k the later right hand sides are updated,
 // r_{k+j} -= A_j dx_k for all j = 1..d-k at once (the paper's "one job per
 // right hand side update", Section 5).
+#include "gang.hpp"
 #include "internal.hpp"
-#include "wg.hpp"
 
 namespace mds {
 
@@ -241,6 +241,77 @@ __global__ void __launch_bounds__(256) k_stage_dx(int k, int N, int n, int d, in
   if (st && status) atomicOr(status, st);
 }
 
+// dx_k = W r_k with each row's dot product on four waves (N <= 64, seg >=
+// 8): element c on wave c mod 4, lanes 4 (c / 4) + q, lane q forming real
+// product q of the complex product as c_mul orders them, the real part of
+// the result then on lane q = 0 and the imaginary part on q = 2, the sum in
+// seg_reduce's order (lead4_sum); the bits are stage_dx_row's.  The n
+// dot products of a stage are too few to fill the chip one wave each, so
+// four lanes a product shorten the stage's chain.
+template <int M>
+__global__ void __launch_bounds__(256) k_stage_dx4(int k, int N, int n, int d, int seg,
+                                                   const double *__restrict__ G,
+                                                   const double *__restrict__ r,
+                                                   double *__restrict__ dx, int32_t *status,
+                                                   const int32_t *gate) {
+  __shared__ double xch[4 * M];
+  if (gate_closed(gate)) return;
+  const long EW = long(n) * N, Er = long(d + 1) * N, Ex = long(d + 1) * n;
+  const int i = blockIdx.x;
+  const int lane = lane_id(), w = threadIdx.x / WAVE, q = lane & 3;
+  const int c = 4 * (lane >> 2) + w;
+  const bool ok = c < N;
+  mdc<M> x = c_zero<M>(), y = c_zero<M>();
+  if (ok) {
+    x = cload<M>(G, EW, long(i) * N + c);
+    y = cload<M>(r, Er, long(k) * N + c);
+  }
+  const mdr<M> p = md_mul<M>((q & 1) ? x.im : x.re, (q == 0 || q == 3) ? y.re : y.im);
+  mdr<M> t = shfl_down_r<M>(p, 1);
+  if (q == 0) t = md_neg<M>(t);
+  mdr<M> s = ok ? md_add<M>(p, t) : md_zero<M>();
+  s = lead4_sum<M>(s, seg, w, lane, true, xch);
+  if (w == 0 && (lane == 0 || lane == 2)) {
+    rstore<M>(dx + size_t(lane >> 1) * M * Ex, Ex, long(k) * n + i, s);
+    if (!md_finite<M>(s) && status) atomicOr(status, MD_ST_NONFINITE);
+  }
+}
+
+// r_{k+j} -= A_j dx_k with each row's dot product on four waves, as in
+// k_stage_dx4 (n <= 64, seg >= 8; the bits are stage_update_row's): for
+// the later stages, whose few rows leave most of the chip idle.
+template <int M>
+__global__ void __launch_bounds__(256) k_stage_update4(int k, int N, int n, int d, int seg,
+                                                       const double *__restrict__ A,
+                                                       const double *__restrict__ dx,
+                                                       double *__restrict__ r,
+                                                       const int32_t *gate) {
+  __shared__ double xch[4 * M];
+  if (gate_closed(gate)) return;
+  const long EA = long(d + 1) * N * n, Er = long(d + 1) * N, Ex = long(d + 1) * n;
+  const long row = blockIdx.x;
+  const int j = int(row / N) + 1;
+  const int i = int(row - long(j - 1) * N);
+  const int lane = lane_id(), w = threadIdx.x / WAVE, q = lane & 3;
+  const int c = 4 * (lane >> 2) + w;
+  const bool ok = c < n;
+  mdc<M> x = c_zero<M>(), y = c_zero<M>();
+  if (ok) {
+    x = cload<M>(A, EA, (long(j) * N + i) * n + c);
+    y = cload<M>(dx, Ex, long(k) * n + c);
+  }
+  const mdr<M> p = md_mul<M>((q & 1) ? x.im : x.re, (q == 0 || q == 3) ? y.re : y.im);
+  mdr<M> t = shfl_down_r<M>(p, 1);
+  if (q == 0) t = md_neg<M>(t);
+  mdr<M> s = ok ? md_add<M>(p, t) : md_zero<M>();
+  s = lead4_sum<M>(s, seg, w, lane, true, xch);
+  if (w == 0 && (lane == 0 || lane == 2)) {
+    const long e = long(k + j) * N + i;
+    double *rp = r + size_t(lane >> 1) * M * Er;
+    rstore<M>(rp, Er, e, md_add<M>(rload<M>(rp, Er, e), md_neg<M>(s)));
+  }
+}
+
 // r_{k+j} -= A_j dx_k for j = 1..d-k: one segment per (j, row)
 template <int M>
 __global__ void __launch_bounds__(256) k_stage_update(int k, int N, int n, int d, int seg,
@@ -312,14 +383,25 @@ int solve_enqueue(int m, int N, int n, int d, const double *QR, const double *vd
     if (rc) return rc;
     const int seg_dx = dot_seg_latency(N);
     const int seg_up = dot_seg_latency(n);
+    // four waves a dot product from three limbs on (a real md product a
+    // quarter of a complex one or less), for the later updates while they
+    // have at most two such rows a SIMD
+    const bool dx4 = Mm >= 3 && N >= 5 && N <= WAVE;
+    const bool up4 = Mm >= 3 && n >= 5 && n <= WAVE;
     for (int k = 0; k <= d; ++k) {
-      {
+      if (dx4) {
+        k_stage_dx4<Mm><<<dim3(unsigned(n)), dim3(256), 0, s>>>(k, N, n, d, seg_dx, G, r, dx,
+                                                                status, gate);
+      } else {
         const long waves = (long(n) * seg_dx + WAVE - 1) / WAVE;
         const long blk = (waves + 3) / 4;
         k_stage_dx<Mm><<<dim3(unsigned(blk)), dim3(256), 0, s>>>(k, N, n, d, seg_dx, G, r, dx,
                                                                   status, gate);
       }
-      if (k < d) {
+      if (k < d && up4 && long(d - k) * N <= 512) {
+        k_stage_update4<Mm><<<dim3(unsigned(long(d - k) * N)), dim3(256), 0, s>>>(
+            k, N, n, d, seg_up, A, dx, r, gate);
+      } else if (k < d) {
         const long rows = long(d - k) * N;
         const long waves = (rows * seg_up + WAVE - 1) / WAVE;
         const long blk = (waves + 3) / 4;
