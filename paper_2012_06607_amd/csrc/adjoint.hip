@@ -14,8 +14,8 @@
 // c_tau(t) x^a(t), so grad c_{tau,j} = -sum_{k>=j} conj(m_{tau,k-j})
 // lambda_{k,i}, m_tau = x^a: either stored by the evaluation pass or
 // recomputed term by term inside the contraction (no buffer).
+#include "dot4.hpp"
 #include "internal.hpp"
-#include "wg.hpp"
 
 namespace mds {
 
@@ -73,6 +73,52 @@ __global__ void __launch_bounds__(256) k_adj_update(int k, int N, int n, int d, 
   if (live && lis == 0) {
     const long e = long(k - j) * n + c;
     cstore<M>(rhs, Er, e, c_sub<M>(cload<M>(rhs, Er, e), s));
+  }
+}
+
+// The same two products with each dot product on four waves (dot4: one
+// real product of each complex product a lane; same bits), from three
+// limbs on while the dot products are at most 64 long: lambda_k[i], one
+// workgroup per i; the update, one workgroup per (j, c), while there are
+// at most 512 of them.
+template <int M>
+__global__ void __launch_bounds__(256) k_adj_lambda4(int k, int N, int n, int d, int seg,
+                                                     const double *__restrict__ W,
+                                                     const double *__restrict__ rhs,
+                                                     double *__restrict__ lam, int32_t *status) {
+  __shared__ double xch[4 * M];
+  const long EW = long(n) * N, Er = long(d + 1) * n, El = long(d + 1) * N;
+  const int i = blockIdx.x;
+  const int lane = lane_id(), w = threadIdx.x / WAVE;
+  const mdr<M> s = dot4<M, true>(n, seg, [&](int c, mdc<M> &x, mdc<M> &y) {
+    x = cload<M>(W, EW, long(c) * N + i);
+    y = cload<M>(rhs, Er, long(k) * n + c);
+  }, xch);
+  if (w == 0 && (lane == 0 || lane == 2)) {
+    rstore<M>(lam + size_t(lane >> 1) * M * El, El, long(k) * N + i, s);
+    if (!md_finite<M>(s) && status) atomicOr(status, MD_ST_NONFINITE);
+  }
+}
+
+template <int M>
+__global__ void __launch_bounds__(256) k_adj_update4(int k, int N, int n, int d, int seg,
+                                                     const double *__restrict__ A,
+                                                     const double *__restrict__ lam,
+                                                     double *__restrict__ rhs) {
+  __shared__ double xch[4 * M];
+  const long row = blockIdx.x;
+  const int j = int(row / n) + 1;
+  const int c = int(row - long(j - 1) * n);
+  const long EA = long(d + 1) * N * n, Er = long(d + 1) * n, El = long(d + 1) * N;
+  const int lane = lane_id(), w = threadIdx.x / WAVE;
+  const mdr<M> s = dot4<M, true>(N, seg, [&](int i, mdc<M> &x, mdc<M> &y) {
+    x = cload<M>(A, EA, (long(j) * N + i) * n + c);
+    y = cload<M>(lam, El, long(k) * N + i);
+  }, xch);
+  if (w == 0 && (lane == 0 || lane == 2)) {
+    const long e = long(k - j) * n + c;
+    double *rp = rhs + size_t(lane >> 1) * M * Er;
+    rstore<M>(rp, Er, e, md_add<M>(rload<M>(rp, Er, e), md_neg<M>(s)));
   }
 }
 
@@ -144,11 +190,20 @@ extern "C" int md_newton_adjoint(int m, int d, const md_system *sys, const doubl
     k_adj_copy<Mm><<<dim3(unsigned(blocks)), dim3(256), 0, s>>>(Er, grad_x, rhs);
     const int seg_l = n >= WAVE ? WAVE : pow2_at_least(n);
     const int seg_u = N >= WAVE ? WAVE : pow2_at_least(N);
+    const bool l4 = Mm >= 3 && n >= 5 && n <= WAVE, u4 = Mm >= 3 && N >= 5 && N <= WAVE;
     for (int k = d; k >= 0; --k) {
-      const long wl = (long(N) * seg_l + WAVE - 1) / WAVE;
-      k_adj_lambda<Mm><<<dim3(unsigned((wl + 3) / 4)), dim3(256), 0, s>>>(k, N, n, d, seg_l, W, rhs,
-                                                                           lam, status);
-      if (k > 0) {
+      if (l4) {
+        k_adj_lambda4<Mm><<<dim3(unsigned(N)), dim3(256), 0, s>>>(k, N, n, d, seg_l, W, rhs, lam,
+                                                                  status);
+      } else {
+        const long wl = (long(N) * seg_l + WAVE - 1) / WAVE;
+        k_adj_lambda<Mm><<<dim3(unsigned((wl + 3) / 4)), dim3(256), 0, s>>>(k, N, n, d, seg_l, W,
+                                                                             rhs, lam, status);
+      }
+      if (k > 0 && u4 && long(k) * n <= 512) {
+        k_adj_update4<Mm><<<dim3(unsigned(long(k) * n)), dim3(256), 0, s>>>(k, N, n, d, seg_u, A,
+                                                                            lam, rhs);
+      } else if (k > 0) {
         const long wu = (long(k) * n * seg_u + WAVE - 1) / WAVE;
         k_adj_update<Mm><<<dim3(unsigned((wu + 3) / 4)), dim3(256), 0, s>>>(k, N, n, d, seg_u, A,
                                                                              lam, rhs);

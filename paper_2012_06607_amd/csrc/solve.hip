@@ -10,7 +10,7 @@
 // N columns of the identity.  After dx_k the later right hand sides are updated,
 // r_{k+j} -= A_j dx_k for all j = 1..d-k at once (the paper's "one job per
 // right hand side update", Section 5).
-#include "gang.hpp"
+#include "dot4.hpp"
 #include "internal.hpp"
 
 namespace mds {
@@ -242,10 +242,8 @@ __global__ void __launch_bounds__(256) k_stage_dx(int k, int N, int n, int d, in
 }
 
 // dx_k = W r_k with each row's dot product on four waves (N <= 64, seg >=
-// 8): element c on wave c mod 4, lanes 4 (c / 4) + q, lane q forming real
-// product q of the complex product as c_mul orders them, the real part of
-// the result then on lane q = 0 and the imaginary part on q = 2, the sum in
-// seg_reduce's order (lead4_sum); the bits are stage_dx_row's.  The n
+// 8; dot4: one real product of each complex product a lane, the sum in
+// seg_reduce's order), the bits of stage_dx_row.  The n
 // dot products of a stage are too few to fill the chip one wave each, so
 // four lanes a product shorten the stage's chain.
 template <int M>
@@ -258,19 +256,11 @@ __global__ void __launch_bounds__(256) k_stage_dx4(int k, int N, int n, int d, i
   if (gate_closed(gate)) return;
   const long EW = long(n) * N, Er = long(d + 1) * N, Ex = long(d + 1) * n;
   const int i = blockIdx.x;
-  const int lane = lane_id(), w = threadIdx.x / WAVE, q = lane & 3;
-  const int c = 4 * (lane >> 2) + w;
-  const bool ok = c < N;
-  mdc<M> x = c_zero<M>(), y = c_zero<M>();
-  if (ok) {
+  const int lane = lane_id(), w = threadIdx.x / WAVE;
+  const mdr<M> s = dot4<M, false>(N, seg, [&](int c, mdc<M> &x, mdc<M> &y) {
     x = cload<M>(G, EW, long(i) * N + c);
     y = cload<M>(r, Er, long(k) * N + c);
-  }
-  const mdr<M> p = md_mul<M>((q & 1) ? x.im : x.re, (q == 0 || q == 3) ? y.re : y.im);
-  mdr<M> t = shfl_down_r<M>(p, 1);
-  if (q == 0) t = md_neg<M>(t);
-  mdr<M> s = ok ? md_add<M>(p, t) : md_zero<M>();
-  s = lead4_sum<M>(s, seg, w, lane, true, xch);
+  }, xch);
   if (w == 0 && (lane == 0 || lane == 2)) {
     rstore<M>(dx + size_t(lane >> 1) * M * Ex, Ex, long(k) * n + i, s);
     if (!md_finite<M>(s) && status) atomicOr(status, MD_ST_NONFINITE);
@@ -292,19 +282,11 @@ __global__ void __launch_bounds__(256) k_stage_update4(int k, int N, int n, int 
   const long row = blockIdx.x;
   const int j = int(row / N) + 1;
   const int i = int(row - long(j - 1) * N);
-  const int lane = lane_id(), w = threadIdx.x / WAVE, q = lane & 3;
-  const int c = 4 * (lane >> 2) + w;
-  const bool ok = c < n;
-  mdc<M> x = c_zero<M>(), y = c_zero<M>();
-  if (ok) {
+  const int lane = lane_id(), w = threadIdx.x / WAVE;
+  const mdr<M> s = dot4<M, false>(n, seg, [&](int c, mdc<M> &x, mdc<M> &y) {
     x = cload<M>(A, EA, (long(j) * N + i) * n + c);
     y = cload<M>(dx, Ex, long(k) * n + c);
-  }
-  const mdr<M> p = md_mul<M>((q & 1) ? x.im : x.re, (q == 0 || q == 3) ? y.re : y.im);
-  mdr<M> t = shfl_down_r<M>(p, 1);
-  if (q == 0) t = md_neg<M>(t);
-  mdr<M> s = ok ? md_add<M>(p, t) : md_zero<M>();
-  s = lead4_sum<M>(s, seg, w, lane, true, xch);
+  }, xch);
   if (w == 0 && (lane == 0 || lane == 2)) {
     const long e = long(k + j) * N + i;
     double *rp = r + size_t(lane >> 1) * M * Er;
