@@ -357,6 +357,7 @@ def single_path(args, B, OC) -> dict:
     r = solve_eval(B, OC, M1, N1, D1, 2, args.single_steps, 5)
     ms, dur, ops = r["ms"], r["dur"], r["ops"]
     qr_tf = ops["md_qr_gang"] / (dur["md_qr"] * 1e-3) / 1e12
+    gang_tf = ops["md_qr_gang"] / (dur["md_qr_gang"] * 1e-3) / 1e12
     return {
         "workload": "qd, n = N = 32, d = 16: eval/diff of a 32x32 system (16 monomials of "
                     "degree <= 4 per equation) + QR of A_0 (cond 1e3) + staggered solve",
@@ -369,6 +370,11 @@ def single_path(args, B, OC) -> dict:
         "k_qr_roofline": {"bound": "alu", "achieved": round(qr_tf, 5), "peak": 78.6,
                           "unit": "TFLOP/s", "frac": round(qr_tf / 78.6, 6),
                           "traffic": traffic_bytes("k_qr")},
+        # the spread form md_newton_step uses (the look-ahead column on
+        # four waves); traffic: the profile's counters, not taken here
+        "k_qr_gang4_roofline": {"bound": "alu", "achieved": round(gang_tf, 5), "peak": 78.6,
+                                "unit": "TFLOP/s", "frac": round(gang_tf / 78.6, 6),
+                                "workgroups": B.md_qr_gang_size(M1, N1, N1), "traffic": None},
         "status": r["status"],
     }
 
