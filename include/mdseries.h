@@ -152,7 +152,10 @@ int md_qr(int m, int N, int n, const double *A0, double *QR, double *vdiag, doub
  * memory after every step (the factorisation is the same, bit for bit;
  * Section 4).  For one large system a workgroup is one CU's issue rate, so
  * the spread shortens the factorisation (octo double, 64 x 64: the column
- * updates of a step in one round instead of sixteen).  sync: one device
+ * updates of a step in one round instead of sixteen).  From three limbs on
+ * and for 5 <= N <= 64 one workgroup takes each step's look-ahead column
+ * and the next reflector on four waves (one real product of each complex
+ * product a lane) and the others the remaining columns.  sync: one device
  * int32 the call clears and uses (caller-owned; calls that share it must not
  * overlap).  The workgroups must be resident together: with the GPU full of
  * other work the barriers wait, and after a bounded wait they set
