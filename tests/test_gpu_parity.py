@@ -294,6 +294,31 @@ def test_qr_flags_singular_column(B):
     assert np.all(host(beta)[:, 2] == 0.0)
 
 
+@pytest.mark.parametrize("m", (4, 8))
+def test_qr_gang_flags_singular_column_like_one_workgroup(B, m):
+    """A zero column in the four-wave look-ahead form of md_qr_gang: the
+    same status bit, zero beta and the same factors bit for bit as md_qr;
+    a NaN entry sets MD_ST_NONFINITE in both."""
+    N = n = 9
+    A0 = I.unit_complex(I.rng(960, m), m, N, n)
+    A0[:, :, :, 4] = 0.0
+    assert B.md_qr_gang_size(m, N, n) > 1
+    QR, vd, beta, st = B.md_qr(dev(A0))
+    QRg, vdg, bg, stg = B.md_qr_gang(dev(A0), sync=torch.zeros(1, dtype=torch.int32, device="cuda"))
+    assert int(host(st)[0]) == int(host(stg)[0])
+    assert int(host(st)[0]) & B.MD_ST_SINGULAR
+    assert np.all(host(bg)[:, 4] == 0.0)
+    assert np.array_equal(host(QRg), host(QR))
+    assert np.array_equal(host(vdg), host(vd))
+    assert np.array_equal(host(bg), host(beta))
+    A0 = I.unit_complex(I.rng(961, m), m, N, n)
+    A0[0, 0, 6, 2] = np.nan
+    _, _, _, st = B.md_qr(dev(A0))
+    _, _, _, stg = B.md_qr_gang(dev(A0), sync=torch.zeros(1, dtype=torch.int32, device="cuda"))
+    assert int(host(st)[0]) & B.MD_ST_NONFINITE
+    assert int(host(stg)[0]) & B.MD_ST_NONFINITE
+
+
 def solve_case(B, m, N, n, d, key):
     if N == n:
         A, b = I.toeplitz_system(key, n, d, m)
