@@ -112,13 +112,15 @@ __global__ void __launch_bounds__(256) k_eval_terms(EvalArgs a) {
 }
 
 // One 64-lane workgroup per term (eval_term_wave): the term's series live
-// in LDS, each coefficient pair's products are split over a group of lanes.
+// in LDS in the compact layout (LDS decides how many terms a CU holds:
+// octo double at degree 4 and 33 coefficients, four instead of three),
+// each coefficient pair's products are split over a group of lanes.
 template <int M>
 __global__ void __launch_bounds__(64) k_eval_terms_wave(EvalArgs a, int r) {
   extern __shared__ double lds_raw[];
   if (gate_closed(a.gate)) return;
-  eval_term_wave<M>(a, blockIdx.x, r, reinterpret_cast<mdc<M> *>(lds_raw),
-                    [] { __syncthreads(); });
+  eval_term_wave<M, true>(a, blockIdx.x, r, reinterpret_cast<mdc<M> *>(lds_raw),
+                          [] { __syncthreads(); });
 }
 
 template <int M>
@@ -154,7 +156,8 @@ int eval_diff_enqueue(int m, int d, const md_system &sys, const double *x, doubl
   return dispatch_m(m, [&](auto Mc) {
     constexpr int Mm = decltype(Mc)::value;
     if (sys.M > 0) {
-      const size_t lds = sizeof(double) * 2 * Mm * size_t(term_lds_series(sys.max_deg)) * (d + 1);
+      const size_t lds =
+          sizeof(double) * 2 * Mm * size_t(term_lds_series(sys.max_deg, true)) * (d + 1);
       if (lds <= lds_limit()) {
         k_eval_terms_wave<Mm><<<dim3(sys.M), dim3(64), lds, s>>>(a, eval_group(d));
       } else {

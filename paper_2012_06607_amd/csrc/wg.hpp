@@ -682,19 +682,30 @@ struct EvalArgs {
 };
 
 
-// LDS series of one term: its factor series, its coefficient series, the
-// forward products P_2..P_D, backward Q_2..Q_{D-1}, cross C_2..C_{D-1}
+// LDS series of one term of degree D <= Dmax: its factor series
+// x_0..x_{D-1}, its coefficient series, the forward products P_2..P_D,
+// backward Q_2..Q_{D-1} and cross C_2..C_{D-1}.  In the compact layout
+// (from Dmax = 3 on; the one-path evaluation, where LDS decides how many
+// terms a CU holds) slots are shared where the lifetimes allow: C_j takes the slot of x_{j-1} (x_1 ..
+// x_{D-2} are last read by the backward products, which end before the
+// first cross product, and no cross product reads them), and the
+// coefficient series takes slot D when D <= 2 (loaded first) or the slot of
+// x_0 when D >= 3 (loaded after the cross products, the last readers of
+// x_0): 3 Dmax - 3 series instead of 4 Dmax - 4.
 struct TermLds {
   int Dmax;
+  bool cmp;  // the compact layout (only with Dmax >= 3)
+  __device__ bool compact() const { return cmp; }
   __device__ int xs(int q) const { return q; }
-  __device__ int cs() const { return Dmax; }
-  __device__ int P(int j) const { return Dmax + 1 + (j - 2); }
-  __device__ int Q(int j) const { return 2 * Dmax + (j - 2); }
-  __device__ int C(int j) const { return 3 * Dmax - 2 + (j - 2); }
+  __device__ int cs(int D) const { return compact() ? (D <= 2 ? D : 0) : Dmax; }
+  __device__ bool cs_late(int D) const { return compact() && D >= 3; }
+  __device__ int P(int j) const { return (compact() ? Dmax : Dmax + 1) + (j - 2); }
+  __device__ int Q(int j) const { return (compact() ? 2 * Dmax - 1 : 2 * Dmax) + (j - 2); }
+  __device__ int C(int j) const { return compact() ? j - 1 : 3 * Dmax - 2 + (j - 2); }
 };
 
-__host__ __device__ inline int term_lds_series(int Dmax) {
-  return Dmax < 2 ? Dmax + 1 : 4 * Dmax - 4;
+__host__ __device__ inline int term_lds_series(int Dmax, bool compact = false) {
+  return Dmax < 2 ? Dmax + 1 : ((compact && Dmax >= 3) ? 3 * Dmax - 3 : 4 * Dmax - 4);
 }
 
 // lane r-group width for degree d: the largest power of two r with
@@ -849,11 +860,12 @@ __device__ __forceinline__ void conv_pair(const mdc<M> *X0, const mdc<M> *Y0, md
 // (d+1) complex numbers): forward and backward products one factor per step,
 // cross products at first positions, then c(t) times the value and the
 // derivatives into the term's workspace slots.  The wave's lanes must all
-// call this; `wave_sync` orders LDS between steps.
-template <int M, class Sync>
+// call this; `wave_sync` orders LDS between steps.  COMPACT: the compact
+// LDS layout of TermLds (sized by term_lds_series(Dmax, true)).
+template <int M, bool COMPACT = false, class Sync>
 __device__ __forceinline__ void eval_term_wave(const EvalArgs &a, int tau, int r, mdc<M> *lds, Sync wave_sync) {
   const int d = a.d, L = d + 1;
-  const TermLds T{a.Dmax};
+  const TermLds T{a.Dmax, COMPACT && a.Dmax >= 3};
   const int lane = lane_id();
   const int D = a.term_ptr[tau + 1] - a.term_ptr[tau];
   if (D > a.Dmax) return;  // the host validates max_deg
@@ -864,10 +876,13 @@ __device__ __forceinline__ void eval_term_wave(const EvalArgs &a, int tau, int r
     const int q = e / L, k = e - q * L;
     S(T.xs(q))[k] = cload<M>(a.x, Ex, long(k) * a.n + v[q]);
   }
-  for (int k = lane; k < L; k += WAVE)
-    S(T.cs())[k] = (k <= a.dc)
-                       ? cload<M>(a.coef, long(a.Mt) * (a.dc + 1), long(tau) * (a.dc + 1) + k)
-                       : c_zero<M>();
+  auto load_cs = [&]() __attribute__((always_inline)) {
+    for (int k = lane; k < L; k += WAVE)
+      S(T.cs(D))[k] = (k <= a.dc)
+                          ? cload<M>(a.coef, long(a.Mt) * (a.dc + 1), long(tau) * (a.dc + 1) + k)
+                          : c_zero<M>();
+  };
+  if (!T.cs_late(D)) load_cs();
   wave_sync();
   const int dcu = a.dc < d ? a.dc : d;
   const long wb = long(tau) * a.S * L;
@@ -881,7 +896,7 @@ __device__ __forceinline__ void eval_term_wave(const EvalArgs &a, int tau, int r
     }
   if (D == 0) {
     for (int k = lane; k < L; k += WAVE)
-      cstore<M>(a.ws, a.Ews, wb + a.lay.val() * L + k, S(T.cs())[k]);
+      cstore<M>(a.ws, a.Ews, wb + a.lay.val() * L + k, S(T.cs(D))[k]);
     return;
   }
   auto Pj = [&](int j) { return j == 1 ? S(T.xs(0)) : S(T.P(j)); };
@@ -898,10 +913,10 @@ __device__ __forceinline__ void eval_term_wave(const EvalArgs &a, int tau, int r
         if (j > 1 && v[j - 1] == v[j - 2]) continue;
         mdc<M> z;
         if (D == 1 && j == 1) {
-          z = S(T.cs())[k];  // d(c x)/dx = c
+          z = S(T.cs(D))[k];  // d(c x)/dx = c
         } else {
           const mdc<M> *Y = j == 0 ? Pj(D) : (j == 1 ? Qj(2) : (j == D ? Pj(D - 1) : S(T.C(j))));
-          z = conv_part<M>(S(T.cs()), dcu, Y, k, 0, 1);
+          z = conv_part<M>(S(T.cs(D)), dcu, Y, k, 0, 1);
           int mult = 1;
           if (j > 0) {
             mult = 0;
@@ -916,10 +931,10 @@ __device__ __forceinline__ void eval_term_wave(const EvalArgs &a, int tau, int r
       }
       return;
     }
-    conv_group<M>(S(T.cs()), dcu, Pj(D), nullptr, d, r, a.ws, a.Ews, wb + a.lay.val() * L, 1);
+    conv_group<M>(S(T.cs(D)), dcu, Pj(D), nullptr, d, r, a.ws, a.Ews, wb + a.lay.val() * L, 1);
     if (D == 1) {
       for (int k = lane; k < L; k += WAVE)
-        cstore<M>(a.ws, a.Ews, wb + a.lay.der(1) * L + k, S(T.cs())[k]);
+        cstore<M>(a.ws, a.Ews, wb + a.lay.der(1) * L + k, S(T.cs(D))[k]);
       return;
     }
     for (int j = 1; j <= D; ++j) {
@@ -927,7 +942,7 @@ __device__ __forceinline__ void eval_term_wave(const EvalArgs &a, int tau, int r
       int mult = 0;
       for (int q = 0; q < D; ++q) mult += (v[q] == v[j - 1]);
       const mdc<M> *cross = (j == 1) ? Qj(2) : (j == D ? Pj(D - 1) : S(T.C(j)));
-      conv_group<M>(S(T.cs()), dcu, cross, nullptr, d, r, a.ws, a.Ews, wb + a.lay.der(j) * L, mult);
+      conv_group<M>(S(T.cs(D)), dcu, cross, nullptr, d, r, a.ws, a.Ews, wb + a.lay.der(j) * L, mult);
     }
   };
   if (D == 1) {
@@ -969,6 +984,10 @@ __device__ __forceinline__ void eval_term_wave(const EvalArgs &a, int tau, int r
   if (a.mono)
     for (int k = lane; k < L; k += WAVE) cstore<M>(a.mono, Em, long(tau) * L + k, Pj(D)[k]);
   wave_sync();
+  if (T.cs_late(D)) {
+    load_cs();
+    wave_sync();
+  }
   coef_products();
 }
 
