@@ -47,9 +47,9 @@ TRAFFIC = {
                        "write_kib": 31923831.896, "write_scale": 262144 / 262144.0,
                        "sha256": "b9b1149694b5c75d377144884ac50a33f96673b82af69c672ee5c76795e76a75",
                        "sources": ('batch.hip', 'batch_kernel.hpp', 'gang.hpp', 'internal.hpp', 'common.hpp', 'md.hpp', 'wg.hpp', 'layout.hpp', 'series.hpp')},
-    "k_qr": {"fetch_kib": 106.0625, "fetch_scale": 262144 / 131088.5, "write_kib": 67.0,
-             "write_scale": 262144 / 262149.25,
-             "sha256": "d6bbfd28c802e246ea83183bfef7b23ba251907f8d55eb5c021b5dced57f527f",
+    "k_qr": {"fetch_kib": 106.0625, "fetch_scale": 262144 / 131088.625, "write_kib": 67.0,
+             "write_scale": 262144 / 262145.125,
+             "sha256": "4c94538ad3b2f3cc03c2db639b07175c83e56dcce9dd25e55e71355aa08d3fde",
              "sources": ('qr.hip', 'gang.hpp', 'internal.hpp', 'common.hpp', 'md.hpp', 'wg.hpp', 'layout.hpp', 'series.hpp')},
 }
 
